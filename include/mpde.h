@@ -1,0 +1,167 @@
+/*
+ * mpde.h -- C ABI of the MI355X (gfx950) solver for the NeuRLP-PDE
+ * least-squares system of Mechanistic PDE Networks (arXiv 2502.18377).
+ *
+ * Problem (Sec. "Mechanistic PDE Networks", Eq. 1 and Eq. 2; Sec. "Linear PDE
+ * Solving With Differentiable Optimization", Eqs. 3-10):
+ *   a batch of linear space-time PDEs  sum_{m in M} c_m(t,x) u_m = b(t,x)
+ *   with initial/boundary data u = omega on a set of faces, on a Cartesian
+ *   grid of D axes (axis 0 = time, the last axis varies fastest in memory).
+ *   Each grid point carries V = 1 + 2D unknowns, in the order
+ *       u, u_{a0}, u_{a0 a0}, u_{a1}, u_{a1 a1}, ...
+ *   (variable 1+2a / 2+2a = first / second derivative along axis a).
+ *   The constraint rows -- equation rows at every point (Eq. 3), boundary
+ *   rows on Dirichlet faces (Eq. 4), 5-point central-difference rows with
+ *   one-sided windows at non-periodic edges (Eq. 5) and forward/backward
+ *   Taylor rows (Eqs. 6-7) -- form A z = d (Eq. 8); the library returns the
+ *   least-squares solution z* of the normal equations A^T A z = A^T d (Eq. 9)
+ *   and gradients through it from the backward saddle-point system (Eq. 11).
+ *
+ * Memory and ownership: every pointer argument is owned by the caller.
+ * Pointers documented "device" must be device memory on the current HIP
+ * device; "host" pointers are host memory.  mpde_build copies what it needs
+ * (coefficients, source, boundary data) into a library-owned hierarchy, so
+ * the caller may free or overwrite its inputs after mpde_build returns.  The
+ * problem handle owns that device memory until mpde_free.
+ *
+ * Batches may be ragged: all instances share D, the boundary types and the
+ * multi-index set, but each has its own shape and steps.  Per-instance
+ * blocks are concatenated in instance order:
+ *   coeff     [sum_b K*N_b]   instance b: K planes of N_b points (mset order)
+ *   rhs       [sum_b N_b]
+ *   bc_values [sum_b N_b]     read on Dirichlet faces only
+ *   z_out     [sum_b V*N_b]   instance b: V planes of N_b points
+ * where N_b = prod_a shape[b][a] and K = popcount(mset).
+ *
+ * Return codes: 0 = success; > 0 = warning (MPDE_WARN_NOT_CONVERGED: at
+ * least one instance did not reach the tolerance, see info.status);
+ * < 0 = error (no partial results).  Arguments are validated on the host
+ * before any device work; no C++ exception crosses this interface.  The last
+ * error message of the calling thread is available from mpde_last_error().
+ * Calls are synchronous with respect to the host: they enqueue on the given
+ * stream and wait for it before returning.  One problem handle must not be
+ * used from two threads at once.
+ */
+#ifndef MPDE_H
+#define MPDE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MPDE_OK = 0,
+  MPDE_WARN_NOT_CONVERGED = 1,
+  MPDE_ERR_INVALID_ARG = -1,
+  MPDE_ERR_UNSUPPORTED = -2,
+  MPDE_ERR_OUT_OF_MEMORY = -3,
+  MPDE_ERR_HIP = -4,
+  MPDE_ERR_NO_DEVICE = -5,
+  MPDE_ERR_BAD_STATE = -6,
+  MPDE_ERR_NONFINITE = -7
+};
+
+enum { MPDE_F32 = 0, MPDE_F64 = 1 };
+
+enum { MPDE_BC_NONE = 0, MPDE_BC_DIRICHLET = 1, MPDE_BC_PERIODIC = 2 };
+
+enum { MPDE_STATUS_CONVERGED = 0, MPDE_STATUS_NOT_CONVERGED = 1, MPDE_STATUS_NONFINITE = 2 };
+
+/* Solver options (multigrid-preconditioned Krylov solve of the normal
+ * equations, Sec. "An Iterative Sparse Multigrid Solver" and the V-cycle
+ * algorithm of the appendix).  Fill with mpde_default_options first. */
+typedef struct {
+  double tol;            /* target relative residual of the normal equations,
+                            ||A^T(d - A z)|| / ||A^T d||, per instance (1e-6) */
+  double inner_tol;      /* relative reduction of each inner Krylov solve
+                            (F32: 1e-4, F64: 1e-10) */
+  int32_t max_outer;     /* outer refinement steps with an FP64 residual (30) */
+  int32_t max_inner;     /* Krylov iterations per outer step (200) */
+  int32_t nu;            /* smoothing steps before and after each coarse
+                            correction (2) */
+  int32_t coarse_min;    /* smallest coarsened periodic axis (4); a
+                            non-periodic axis stops at >= 5 points */
+  int32_t check_every;   /* Krylov iterations between host convergence checks (2) */
+  int32_t max_levels;    /* cap on grid levels including the finest (16) */
+  int32_t reserved[8];
+} mpde_options;
+
+/* Problem description (the encoder outputs of Eq. 2 with uniform steps). */
+typedef struct {
+  int32_t dtype;          /* MPDE_F32 or MPDE_F64: element type of coeff, rhs,
+                             bc_values, z_out, g_z and the gradient outputs */
+  int32_t ndim;           /* D = 2 or 3 axes, axis 0 = time */
+  int32_t batch;          /* B >= 1 instances */
+  const int32_t *shape;   /* host [B][D] points per axis; every axis >= 5 */
+  const double *step;     /* host [B][D] uniform step per axis, > 0 */
+  int32_t bc_lo[3];       /* per axis, face at index 0: MPDE_BC_*  */
+  int32_t bc_hi[3];       /* per axis, face at index n-1; PERIODIC must be set
+                             on both faces of an axis or on neither */
+  uint32_t mset;          /* bit v set = variable v has a coefficient field in
+                             the equation row; bits >= V must be clear; at
+                             least one bit set */
+  const void *coeff;      /* device, see layout above */
+  const void *rhs;        /* device, the source b of Eq. 1 */
+  const void *bc_values;  /* device, omega of Eq. 4 */
+  void *stream;           /* hipStream_t to run on (NULL = null stream) */
+  const mpde_options *opts; /* host, NULL = defaults */
+} mpde_desc;
+
+/* Per-call report; every array is host memory of length >= batch, or NULL. */
+typedef struct {
+  int32_t *iters;         /* total inner Krylov iterations per instance */
+  int32_t *outer;         /* outer refinement steps per instance */
+  double *relres;         /* final relative residual of the normal equations */
+  int32_t *status;        /* MPDE_STATUS_* */
+  double seconds;         /* wall time of the call (output) */
+} mpde_info;
+
+typedef struct mpde_problem mpde_problem;   /* opaque, library-owned */
+
+/* Fill *o with the defaults above.  Returns MPDE_ERR_INVALID_ARG if o is NULL. */
+int mpde_default_options(mpde_options *o);
+
+/* Validate *d (host only), plan the grid hierarchy (each spatial axis is
+ * halved while it stays at or above the minimum size; time is never
+ * coarsened), copy and coarsen the coefficient fields to every level and
+ * factor the coarsest-level operators.  On success *out receives a new
+ * handle that the caller releases with mpde_free.  Errors: INVALID_ARG,
+ * UNSUPPORTED, OUT_OF_MEMORY, HIP, NO_DEVICE.  Sec. "An Iterative Sparse
+ * Multigrid Solver" (coarse grids by halving with doubled steps, coefficients
+ * coarsened by interpolation). */
+int mpde_build(const mpde_desc *d, mpde_problem **out);
+
+/* Solve A^T A z = A^T d (Eq. 9) for every instance and write z* to z_out
+ * (device, [sum_b V*N_b], dtype of the problem).  Keeps an internal copy of
+ * u* for mpde_solve_adjoint.  info may be NULL.  Returns 0, or
+ * MPDE_WARN_NOT_CONVERGED (z_out holds the best iterate), or an error. */
+int mpde_solve(mpde_problem *p, void *z_out, mpde_info *info);
+
+/* Backward pass (Eq. 11 and the gradient formulas after it): given
+ * g_z = dl/dz* (device, [sum_b V*N_b]) solve A^T A d_z = g_z, form
+ * d_lambda = -A d_z and lambda* = d - A z*, and write
+ *   grad_coeff [sum_b K*N_b] = d_lambda_E z*_m + lambda*_E d_z_m  (per point)
+ *   grad_rhs   [sum_b N_b]   = -d_lambda_E
+ *   grad_bc    [sum_b N_b]   = -d_lambda_B on constrained points, 0 elsewhere
+ * Any of the three outputs may be NULL.  Requires a prior successful
+ * mpde_solve on p (else MPDE_ERR_BAD_STATE). */
+int mpde_solve_adjoint(mpde_problem *p, const void *g_z, void *grad_coeff,
+                       void *grad_rhs, void *grad_bc, mpde_info *info);
+
+/* Release the handle and its device memory; NULL is a no-op. */
+void mpde_free(mpde_problem *p);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *mpde_last_error(void);
+
+/* Grid levels planned for instance b (0 if p is NULL or b out of range);
+ * if shapes is not NULL it receives levels*D points-per-axis values. */
+int mpde_levels(const mpde_problem *p, int32_t b, int32_t *shapes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPDE_H */

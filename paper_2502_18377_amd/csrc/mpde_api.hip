@@ -1,0 +1,825 @@
+// Host runtime of the MI355X NeuRLP-PDE solver: the C ABI of include/mpde.h.
+//
+// Solve structure (paper: Sec. "An Iterative Sparse Multigrid Solver" and
+// the V-cycle algorithm of the appendix):
+//   * outer loop: FP64 iterate u and FP64 residual g - S u formed row by row
+//     as A_u^T Pi (d - A u) (never as A^T d - A^T A u), stop at the requested
+//     normal-equation relative residual;
+//   * inner solve: conjugate gradients in the problem's precision (FP32 or
+//     FP64) on S e = r, preconditioned by one multigrid V-cycle;
+//   * V-cycle: Chebyshev/point-Jacobi smoothing (a parallel replacement of
+//     the paper's Gauss-Seidel relaxation), residual, restriction by the
+//     transpose of linear interpolation, recursion, prolongation by linear
+//     interpolation, correction, smoothing; the coarsest grid is solved
+//     exactly with a dense inverse built once per problem;
+//   * grids: every spatial axis is halved with its step doubled while it
+//     stays at or above the minimum size (time is never coarsened, because the
+//     reduced operator couples space far more strongly than time); coarse
+//     operators are re-discretised from coefficient fields coarsened by
+//     normalised full weighting, with Taylor and first-difference rows
+//     weighted 2^-k and second-difference rows 4^-k (k = halvings of that
+//     axis), which keeps each derivative unknown's stiffness level-invariant.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <new>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mpde.h"
+#include "mpde_internal.hpp"
+#include "mpde_kernels.hpp"
+
+using namespace mpde;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+struct HipError {
+  hipError_t e;
+  const char* what;
+};
+
+#define HIPCHK(x)                                                   \
+  do {                                                              \
+    hipError_t _e = (x);                                            \
+    if (_e != hipSuccess) throw HipError{_e, #x};                   \
+  } while (0)
+
+constexpr int kMaxDense = 2048;
+
+// ---------------------------------------------------------------- stencils
+// 5-point weights from the moment conditions sum_k w_k o_k^p / p! = [p == q]
+// (Gaussian elimination with partial pivoting in double precision).
+void fd_table(int q, double out[5][5]) {
+  for (int pos = 0; pos < 5; ++pos) {
+    double M[5][6];
+    for (int p = 0; p < 5; ++p) {
+      double fact = 1;
+      for (int t = 2; t <= p; ++t) fact *= t;
+      for (int k = 0; k < 5; ++k) M[p][k] = std::pow((double)(k - pos), p) / fact;
+      M[p][5] = (p == q) ? 1.0 : 0.0;
+    }
+    for (int c = 0; c < 5; ++c) {
+      int piv = c;
+      for (int r = c + 1; r < 5; ++r)
+        if (std::fabs(M[r][c]) > std::fabs(M[piv][c])) piv = r;
+      for (int k = 0; k < 6; ++k) std::swap(M[c][k], M[piv][k]);
+      for (int r = 0; r < 5; ++r) {
+        if (r == c) continue;
+        const double f = M[r][c] / M[c][c];
+        for (int k = c; k < 6; ++k) M[r][k] -= f * M[c][k];
+      }
+    }
+    for (int k = 0; k < 5; ++k) out[pos][k] = M[k][5] / M[k][k];
+  }
+}
+
+template <typename T>
+T* dalloc(size_t n) {
+  void* p = nullptr;
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc(&p, n * sizeof(T));
+  if (e != hipSuccess) throw HipError{e, "hipMalloc"};
+  return (T*)p;
+}
+
+// A host work table and its device copy, with per-instance block ranges.
+struct Table {
+  std::vector<Work> h;
+  std::vector<int> bstart;     // [B+1]
+  Work* d = nullptr;
+  int* d_bstart = nullptr;
+  int nb() const { return (int)h.size(); }
+};
+
+struct Level {
+  std::vector<LInst> h;        // [B]; N = 0 for instances without this level
+  LInst* d = nullptr;
+  long long npts = 0;          // total points of this level
+  Table all, smooth, dense;    // all instances / non-coarsest / coarsest (rows)
+  void* coef = nullptr;        // TC [K planes per instance]
+  void *x = nullptr, *r = nullptr, *dd = nullptr, *b = nullptr, *gam = nullptr, *dinv = nullptr;
+};
+
+}  // namespace
+
+struct mpde_problem {
+  int dtype = 0, D = 0, B = 0, K = 0, V = 0;
+  uint32_t mset = 0;
+  CIdx ci{};
+  mpde_options opt{};
+  hipStream_t st = nullptr;
+  int bc_lo[3] = {0, 0, 0}, bc_hi[3] = {0, 0, 0};
+  std::vector<std::vector<std::array<int, 3>>> lshape;   // [b][level]
+  std::vector<int> nlev;
+  std::vector<Level> lv;
+  std::vector<long long> zoff_h;
+  long long* zoff = nullptr;
+  void *f = nullptr, *w = nullptr;                          // TC, level-0 layout
+  double *u64 = nullptr, *r64 = nullptr, *g64 = nullptr, *ghat = nullptr, *vloc = nullptr, *du64 = nullptr;
+  void *e = nullptr, *rk = nullptr, *zk = nullptr, *pk = nullptr, *qk = nullptr;   // TV, level 0
+  double* partial = nullptr;
+  double *rz_new = nullptr, *rz = nullptr, *beta = nullptr, *pq = nullptr, *alpha = nullptr, *rn2 = nullptr,
+         *r0n2 = nullptr, *atd2 = nullptr, *scale = nullptr, *iscale = nullptr;
+  int *active = nullptr, *iters = nullptr, *flag = nullptr;
+  void* Sinv = nullptr;                                    // TV dense inverses
+  bool has_solution = false;
+  std::vector<void*> owned;
+  ~mpde_problem() {
+    for (void* p : owned) (void)hipFree(p);
+  }
+  template <typename T>
+  T* alloc(size_t n) {
+    T* p = dalloc<T>(n);
+    owned.push_back(p);
+    return p;
+  }
+};
+
+namespace {
+
+void upload_table(mpde_problem* P, Table& t) {
+  t.d = P->alloc<Work>(std::max<size_t>(t.h.size(), 1));
+  t.d_bstart = P->alloc<int>(t.bstart.size());
+  if (!t.h.empty()) HIPCHK(hipMemcpy(t.d, t.h.data(), t.h.size() * sizeof(Work), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(t.d_bstart, t.bstart.data(), t.bstart.size() * sizeof(int), hipMemcpyHostToDevice));
+}
+
+// Work items over the points of the selected instances (instance-major).
+void make_table(Table& t, const std::vector<LInst>& h, int B, const std::vector<int>& sel) {
+  t.h.clear();
+  t.bstart.assign(B + 1, 0);
+  for (int b = 0; b < B; ++b) {
+    t.bstart[b] = (int)t.h.size();
+    if (!sel[b]) continue;
+    for (int s = 0; s < h[b].N; s += kBlock) t.h.push_back(Work{b, s});
+  }
+  t.bstart[B] = (int)t.h.size();
+}
+
+template <typename TV>
+struct Ptr {
+  static TV* v(void* p) { return (TV*)p; }
+};
+
+// ----------------------------------------------------------------- solver
+template <typename TV, typename TC>
+struct Solver {
+  mpde_problem* P;
+  hipStream_t st;
+  int D;
+  explicit Solver(mpde_problem* p) : P(p), st(p->st), D(p->D) {}
+
+  TV* V(void* p) { return (TV*)p; }
+  TC* C(void* p) { return (TC*)p; }
+
+  void finish(const Table& t, double* out) { launch_finish_sum(st, P->partial, t.d_bstart, P->B, out); }
+
+  // y = S u on level l for the instances of table t.
+  void apply(int l, const Table& t, TV* u, TV* out, int mode, double* partial) {
+    Level& L = P->lv[l];
+    launch_gamma<TV, TV, TC>(D, st, t.d, t.nb(), L.d, P->ci, u, C(L.coef), C(P->f), 0, V(L.gam));
+    launch_gather<TV, TV, TC>(D, st, t.d, t.nb(), L.d, P->ci, u, V(L.gam), C(L.coef), C(P->w), 0, mode, out,
+                              nullptr, nullptr, nullptr, nullptr, nullptr, 0, partial);
+  }
+
+  void chebyshev(int l, TV* x, int nu) {
+    Level& L = P->lv[l];
+    const Table& t = L.smooth;
+    for (int s = 0; s < nu; ++s) {
+      launch_gamma<TV, TV, TC>(D, st, t.d, t.nb(), L.d, P->ci, V(L.dd), C(L.coef), C(P->f), 0, V(L.gam));
+      launch_gather<TV, TV, TC>(D, st, t.d, t.nb(), L.d, P->ci, V(L.dd), V(L.gam), C(L.coef), C(P->w), 0, G_CHEB,
+                                nullptr, nullptr, x, V(L.r), V(L.dd), V(L.dinv), s, nullptr);
+    }
+  }
+
+  // x = V-cycle(b) on level l (x and b are level-l vectors).
+  void vcycle(int l, TV* b, TV* x) {
+    Level& L = P->lv[l];
+    const int nu = P->opt.nu;
+    if (L.dense.nb() > 0) launch_dense_apply<TV>(st, L.dense.d, L.dense.nb(), L.d, V(P->Sinv), b, x);
+    if (L.smooth.nb() == 0) return;
+    const Table& t = L.smooth;
+    launch_cheb_init<TV>(st, t.d, t.nb(), L.d, b, V(L.dinv), x, V(L.r), V(L.dd));
+    chebyshev(l, x, nu);
+    Level& Cc = P->lv[l + 1];
+    launch_restrict<TV>(D, st, Cc.all.d, Cc.all.nb(), L.d, Cc.d, V(L.r), V(Cc.b));
+    vcycle(l + 1, V(Cc.b), V(Cc.x));
+    launch_prolong_add<TV>(D, st, t.d, t.nb(), L.d, Cc.d, V(Cc.x), x);
+    launch_gamma<TV, TV, TC>(D, st, t.d, t.nb(), L.d, P->ci, x, C(L.coef), C(P->f), 0, V(L.gam));
+    launch_gather<TV, TV, TC>(D, st, t.d, t.nb(), L.d, P->ci, x, V(L.gam), C(L.coef), C(P->w), 0, G_RESID, V(L.r),
+                              b, nullptr, nullptr, V(L.dd), V(L.dinv), 0, nullptr);
+    chebyshev(l, x, nu);
+  }
+
+  // PCG on S e = rk (level 0), e = 0 start; instances with active=0 stay frozen.
+  void pcg(double rel_tol, int max_it) {
+    Level& L0 = P->lv[0];
+    const Table& t = L0.all;
+    const int B = P->B;
+    launch_fill<TV>(st, t.d, t.nb(), L0.d, V(P->e), 0.0);
+    launch_fill<TV>(st, t.d, t.nb(), L0.d, V(P->pk), 0.0);
+    launch_dot<double, TV>(st, t.d, t.nb(), L0.d, V(P->rk), V(P->rk), P->partial);
+    finish(t, P->r0n2);
+    const double tol2 = rel_tol * rel_tol;
+    std::vector<int> act(B);
+    for (int it = 0; it < max_it; ++it) {
+      vcycle(0, V(P->rk), V(P->zk));
+      launch_dot<double, TV>(st, t.d, t.nb(), L0.d, V(P->rk), V(P->zk), P->partial);
+      finish(t, P->rz_new);
+      launch_pcg_scalars(st, 0, B, it == 0, tol2, P->rz_new, P->rz, P->beta, P->pq, P->alpha, P->rn2, P->r0n2,
+                         P->active, P->iters);
+      launch_update_p<TV>(st, t.d, t.nb(), L0.d, P->beta, V(P->zk), V(P->pk));
+      apply(0, t, V(P->pk), V(P->qk), G_STORE_DOT, P->partial);
+      finish(t, P->pq);
+      launch_pcg_scalars(st, 1, B, 0, tol2, P->rz_new, P->rz, P->beta, P->pq, P->alpha, P->rn2, P->r0n2, P->active,
+                         P->iters);
+      launch_update_xr<TV>(st, t.d, t.nb(), L0.d, P->alpha, V(P->pk), V(P->qk), V(P->e), V(P->rk), P->partial);
+      finish(t, P->rn2);
+      launch_pcg_scalars(st, 2, B, 0, tol2, P->rz_new, P->rz, P->beta, P->pq, P->alpha, P->rn2, P->r0n2, P->active,
+                         P->iters);
+      if ((it + 1) % std::max(1, P->opt.check_every) == 0 || it + 1 == max_it) {
+        HIPCHK(hipMemcpyAsync(act.data(), P->active, B * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        bool any = false;
+        for (int b = 0; b < B; ++b) any |= act[b] != 0;
+        if (!any) break;
+      }
+    }
+  }
+
+  // FP64 residual r64 = rhs - S u64 on level 0, and ||r64||^2 per instance
+  // into rn2 (adjoint: rhs = ghat, sigma = 0; forward: sigma = 1, rhs = g).
+  void residual64(bool adjoint, double* u64) {
+    Level& L0 = P->lv[0];
+    const Table& t = L0.all;
+    launch_gamma<double, double, TC>(D, st, t.d, t.nb(), L0.d, P->ci, u64, C(L0.coef), C(P->f), adjoint ? 0 : 1,
+                                     P->g64);
+    launch_gather<double, double, TC>(D, st, t.d, t.nb(), L0.d, P->ci, u64, P->g64, C(L0.coef), C(P->w),
+                                      adjoint ? 0 : 1, G_RESID, P->r64, adjoint ? P->ghat : nullptr, nullptr,
+                                      nullptr, nullptr, nullptr, 0, nullptr);
+    launch_dot<double, double>(st, t.d, t.nb(), L0.d, P->r64, P->r64, P->partial);
+    finish(t, P->rn2);
+  }
+
+  // Outer refinement; returns the code; fills info arrays.
+  int refine(bool adjoint, double* u64, const double* norm2, mpde_info* info) {
+    Level& L0 = P->lv[0];
+    const Table& t = L0.all;
+    const int B = P->B;
+    std::vector<double> rn(B), nb(B);
+    std::vector<int> outer(B, 0), status(B, MPDE_STATUS_NOT_CONVERGED), itv(B, 0);
+    HIPCHK(hipMemcpyAsync(nb.data(), norm2, B * sizeof(double), hipMemcpyDeviceToHost, st));
+    launch_fill<double>(st, t.d, t.nb(), L0.d, u64, 0.0);
+    HIPCHK(hipMemsetAsync(P->iters, 0, B * sizeof(int), st));
+    const double inner_tol = P->opt.inner_tol > 0 ? P->opt.inner_tol : (P->dtype == MPDE_F32 ? 1e-4 : 1e-10);
+    std::vector<double> relres(B, 1.0), sc(B), isc(B);
+    std::vector<int> act(B);
+    int code = MPDE_WARN_NOT_CONVERGED;
+    for (int k = 0; k <= P->opt.max_outer; ++k) {
+      residual64(adjoint, u64);
+      HIPCHK(hipMemcpyAsync(rn.data(), P->rn2, B * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      bool all = true;
+      for (int b = 0; b < B; ++b) {
+        const double den = nb[b] > 0 ? std::sqrt(nb[b]) : 1.0;
+        relres[b] = std::sqrt(rn[b]) / den;
+        if (!std::isfinite(relres[b])) status[b] = MPDE_STATUS_NONFINITE;
+        else if (relres[b] <= P->opt.tol || rn[b] == 0.0) status[b] = MPDE_STATUS_CONVERGED;
+        else status[b] = MPDE_STATUS_NOT_CONVERGED;
+        act[b] = status[b] == MPDE_STATUS_NOT_CONVERGED;
+        all &= !act[b];
+        sc[b] = (rn[b] > 0 && std::isfinite(rn[b])) ? 1.0 / std::sqrt(rn[b]) : 0.0;
+        isc[b] = (rn[b] > 0 && std::isfinite(rn[b])) ? std::sqrt(rn[b]) : 0.0;
+      }
+      if (all || k == P->opt.max_outer) { code = all ? MPDE_OK : MPDE_WARN_NOT_CONVERGED; break; }
+      for (int b = 0; b < B; ++b) if (act[b]) outer[b] += 1;
+      HIPCHK(hipMemcpyAsync(P->scale, sc.data(), B * sizeof(double), hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(P->iscale, isc.data(), B * sizeof(double), hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(P->active, act.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
+      launch_copy_scale<double, TV>(st, t.d, t.nb(), L0.d, P->r64, V(P->rk), P->scale, 0);
+      pcg(inner_tol, P->opt.max_inner);
+      launch_copy_scale<TV, double>(st, t.d, t.nb(), L0.d, V(P->e), u64, P->iscale, 1);
+    }
+    HIPCHK(hipMemcpyAsync(itv.data(), P->iters, B * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    bool nonfinite = false;
+    for (int b = 0; b < B; ++b) nonfinite |= status[b] == MPDE_STATUS_NONFINITE;
+    if (info) {
+      for (int b = 0; b < B; ++b) {
+        if (info->iters) info->iters[b] = itv[b];
+        if (info->outer) info->outer[b] = outer[b];
+        if (info->relres) info->relres[b] = relres[b];
+        if (info->status) info->status[b] = status[b];
+      }
+    }
+    if (nonfinite && code == MPDE_OK) code = MPDE_WARN_NOT_CONVERGED;
+    return code;
+  }
+
+  // ---------------------------------------------------------- build parts
+  void setup_level_operators() {
+    const int nlevels = (int)P->lv.size();
+    for (int l = 0; l < nlevels; ++l) {
+      Level& L = P->lv[l];
+      launch_diag<TV, TC>(D, st, L.all.d, L.all.nb(), L.d, P->ci, C(L.coef), V(L.dinv));
+    }
+    // Chebyshev interval: power iteration x <- D^-1 S x (12 steps) and the
+    // Rayleigh quotient x^T S x / x^T D x; hi = 1.1 * estimate, lo = hi / 10.
+    for (int l = 0; l < nlevels; ++l) {
+      Level& L = P->lv[l];
+      if (L.smooth.nb() == 0) continue;
+      const Table& t = L.smooth;
+      launch_hash_fill<TV>(st, t.d, t.nb(), L.d, V(L.x), 12345u + l);
+      for (int it = 0; it < 12; ++it) {
+        apply(l, t, V(L.x), V(L.r), G_STORE, nullptr);
+        launch_mul_dinv<TV>(st, t.d, t.nb(), L.d, V(L.dinv), V(L.r), V(L.x), P->partial);  // partial: x^T D x
+      }
+      finish(t, P->pq);
+      apply(l, t, V(L.x), V(L.r), G_STORE_DOT, P->partial);                                 // x^T S x
+      finish(t, P->rz);
+      std::vector<double> vsv(P->B), vdv(P->B);
+      HIPCHK(hipMemcpyAsync(vsv.data(), P->rz, P->B * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(vdv.data(), P->pq, P->B * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      for (int b = 0; b < P->B; ++b) {
+        if (L.h[b].N == 0 || L.h[b].coarsest) continue;
+        double lam = vdv[b] > 0 ? vsv[b] / vdv[b] : 0.0;
+        if (!(lam > 0) || !std::isfinite(lam)) lam = 4.0;
+        const double hi = 1.1 * lam, lo = hi / 10.0;
+        L.h[b].cheb_theta = 0.5 * (hi + lo);
+        L.h[b].cheb_delta = 0.5 * (hi - lo);
+      }
+      HIPCHK(hipMemcpyAsync(L.d, L.h.data(), L.h.size() * sizeof(LInst), hipMemcpyHostToDevice, st));
+    }
+  }
+
+  // Dense inverses of the coarsest operators: probe S with unit vectors (one
+  // virtual instance per column), invert in FP64 by Gauss-Jordan, store in TV.
+  void build_dense() {
+    const int B = P->B;
+    std::vector<long long> doff(B, -1), moff;
+    std::vector<int> mn;
+    long long tot = 0, totsq = 0;
+    for (int b = 0; b < B; ++b) {
+      const int lc = P->nlev[b] - 1;
+      const int n = P->lv[lc].h[b].N;
+      doff[b] = totsq;
+      totsq += (long long)n * n;
+    }
+    (void)tot;
+    double* U = dalloc<double>(totsq);
+    double* GM = dalloc<double>(totsq);
+    double* SC = dalloc<double>(totsq);
+    int* dfail = dalloc<int>(B);
+    struct Free { std::vector<void*> v; ~Free() { for (void* p : v) (void)hipFree(p); } } fr{{U, GM, SC, dfail}};
+    HIPCHK(hipMemsetAsync(U, 0, totsq * sizeof(double), st));
+    HIPCHK(hipMemsetAsync(dfail, 0, B * sizeof(int), st));
+    for (int l = 0; l < (int)P->lv.size(); ++l) {
+      Level& L = P->lv[l];
+      std::vector<LInst> vi;
+      std::vector<int> col;
+      std::vector<Work> wk;
+      for (int b = 0; b < B; ++b) {
+        if (L.h[b].N == 0 || !L.h[b].coarsest) continue;
+        const int n = L.h[b].N;
+        for (int c = 0; c < n; ++c) {
+          LInst q = L.h[b];
+          q.voff = doff[b] + (long long)c * n;
+          const int id = (int)vi.size();
+          vi.push_back(q);
+          col.push_back(c);
+          for (int s = 0; s < n; s += kBlock) wk.push_back(Work{id, s});
+        }
+      }
+      if (vi.empty()) continue;
+      LInst* dvi = dalloc<LInst>(vi.size());
+      int* dcol = dalloc<int>(col.size());
+      Work* dwk = dalloc<Work>(wk.size());
+      fr.v.push_back(dvi); fr.v.push_back(dcol); fr.v.push_back(dwk);
+      HIPCHK(hipMemcpyAsync(dvi, vi.data(), vi.size() * sizeof(LInst), hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(dcol, col.data(), col.size() * sizeof(int), hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(dwk, wk.data(), wk.size() * sizeof(Work), hipMemcpyHostToDevice, st));
+      launch_set_unit(st, dvi, dcol, (int)vi.size(), U);
+      launch_gamma<double, double, TC>(D, st, dwk, (int)wk.size(), dvi, P->ci, U, C(L.coef), C(P->f), 0, GM);
+      launch_gather<double, double, TC>(D, st, dwk, (int)wk.size(), dvi, P->ci, U, GM, C(L.coef), C(P->w), 0,
+                                        G_STORE, SC, nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr);
+      HIPCHK(hipStreamSynchronize(st));
+    }
+    std::vector<long long> offs;
+    std::vector<int> ns;
+    for (int b = 0; b < B; ++b) {
+      offs.push_back(doff[b]);
+      ns.push_back(P->lv[P->nlev[b] - 1].h[b].N);
+    }
+    long long* doffs = dalloc<long long>(B);
+    int* dns = dalloc<int>(B);
+    fr.v.push_back(doffs); fr.v.push_back(dns);
+    HIPCHK(hipMemcpyAsync(doffs, offs.data(), B * sizeof(long long), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(dns, ns.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
+    launch_gauss_jordan(st, B, SC, doffs, dns, dfail);
+    P->Sinv = P->alloc<TV>(totsq);
+    launch_convert_dense<TV>(st, SC, V(P->Sinv), totsq);
+    std::vector<int> hf(B);
+    HIPCHK(hipMemcpyAsync(hf.data(), dfail, B * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int b = 0; b < B; ++b)
+      if (hf[b]) throw std::string("coarsest-grid operator of instance " + std::to_string(b) +
+                                   " is not positive definite (rank-deficient problem?)");
+    for (int l = 0; l < (int)P->lv.size(); ++l) {
+      Level& L = P->lv[l];
+      bool any = false;
+      for (int b = 0; b < B; ++b)
+        if (L.h[b].N && L.h[b].coarsest) { L.h[b].doff = doff[b]; any = true; }
+      if (any) HIPCHK(hipMemcpyAsync(L.d, L.h.data(), L.h.size() * sizeof(LInst), hipMemcpyHostToDevice, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+  }
+
+  void atd_norm() {
+    Level& L0 = P->lv[0];
+    launch_atd_norm<TC>(D, st, L0.all.d, L0.all.nb(), L0.d, P->ci, C(L0.coef), C(P->f), C(P->w), P->partial);
+    finish(L0.all, P->atd2);
+  }
+
+  void alloc_vectors() {
+    for (auto& L : P->lv) {
+      L.coef = P->alloc<TC>((size_t)P->K * L.npts);
+      L.x = P->alloc<TV>(L.npts);
+      L.r = P->alloc<TV>(L.npts);
+      L.dd = P->alloc<TV>(L.npts);
+      L.b = P->alloc<TV>(L.npts);
+      L.gam = P->alloc<TV>(L.npts);
+      L.dinv = P->alloc<TV>(L.npts);
+    }
+    const long long n0 = P->lv[0].npts;
+    P->f = P->alloc<TC>(n0);
+    P->w = P->alloc<TC>(n0);
+    P->e = P->alloc<TV>(n0);
+    P->rk = P->alloc<TV>(n0);
+    P->zk = P->alloc<TV>(n0);
+    P->pk = P->alloc<TV>(n0);
+    P->qk = P->alloc<TV>(n0);
+  }
+
+  void coarsen_all() {
+    for (int l = 0; l + 1 < (int)P->lv.size(); ++l) {
+      Level& L = P->lv[l];
+      Level& Cc = P->lv[l + 1];
+      launch_coarsen_coef<TC>(D, st, Cc.all.d, Cc.all.nb(), L.d, Cc.d, P->K, C(L.coef), C(Cc.coef));
+    }
+  }
+
+  template <typename TO>
+  void output(TO* z) {
+    Level& L0 = P->lv[0];
+    launch_output<TC, TO>(D, st, L0.all.d, L0.all.nb(), L0.d, P->ci, P->u64, C(L0.coef), C(P->f), z, P->zoff);
+  }
+
+  template <typename TG>
+  int adjoint(const TG* gz, TG* gc, TG* gf, TG* gw, mpde_info* info) {
+    Level& L0 = P->lv[0];
+    const Table& t = L0.all;
+    launch_adj_local<TC, TG>(D, st, t.d, t.nb(), L0.d, P->ci, C(L0.coef), gz, P->zoff, P->vloc);
+    launch_adj_rhs<TC, TG>(D, st, t.d, t.nb(), L0.d, P->ci, C(L0.coef), gz, P->zoff, P->vloc, P->ghat);
+    launch_dot<double, double>(st, t.d, t.nb(), L0.d, P->ghat, P->ghat, P->partial);
+    finish(t, P->pq);
+    // The adjoint tolerance is relative to ||g^||; keep pq as the norm.
+    HIPCHK(hipMemcpyAsync(P->scale, P->pq, P->B * sizeof(double), hipMemcpyDeviceToDevice, st));
+    int code = refine(true, P->du64, P->scale, info);
+    launch_adj_grad<TC, TG>(D, st, t.d, t.nb(), L0.d, P->ci, C(L0.coef), C(P->f), P->u64, P->du64, gz, P->zoff, gc,
+                            gf, gw);
+    HIPCHK(hipStreamSynchronize(st));
+    return code;
+  }
+};
+
+}  // namespace
+
+// ================================================================== build
+namespace {
+
+int validate(const mpde_desc* d, mpde_options& opt) {
+  if (!d) return fail(MPDE_ERR_INVALID_ARG, "descriptor is NULL");
+  if (d->dtype != MPDE_F32 && d->dtype != MPDE_F64) return fail(MPDE_ERR_INVALID_ARG, "dtype must be MPDE_F32 or MPDE_F64");
+  if (d->ndim != 2 && d->ndim != 3) return fail(MPDE_ERR_UNSUPPORTED, "ndim must be 2 or 3");
+  if (d->batch < 1) return fail(MPDE_ERR_INVALID_ARG, "batch must be >= 1");
+  if (!d->shape || !d->step) return fail(MPDE_ERR_INVALID_ARG, "shape and step must be non-NULL host arrays");
+  if (!d->coeff || !d->rhs || !d->bc_values) return fail(MPDE_ERR_INVALID_ARG, "coeff, rhs and bc_values must be non-NULL");
+  const int D = d->ndim, V = 1 + 2 * D;
+  if (d->mset == 0 || (d->mset >> V) != 0) return fail(MPDE_ERR_INVALID_ARG, "mset must be nonzero with bits < V = 1+2D");
+  for (int a = 0; a < D; ++a) {
+    for (int v : {d->bc_lo[a], d->bc_hi[a]})
+      if (v < MPDE_BC_NONE || v > MPDE_BC_PERIODIC) return fail(MPDE_ERR_INVALID_ARG, "boundary code out of range");
+    if ((d->bc_lo[a] == MPDE_BC_PERIODIC) != (d->bc_hi[a] == MPDE_BC_PERIODIC))
+      return fail(MPDE_ERR_INVALID_ARG, "periodic must be set on both faces of an axis");
+  }
+  for (int b = 0; b < d->batch; ++b) {
+    long long N = 1;
+    for (int a = 0; a < D; ++a) {
+      const int n = d->shape[b * D + a];
+      const double s = d->step[b * D + a];
+      if (n < 5) return fail(MPDE_ERR_INVALID_ARG, "every axis needs at least 5 points");
+      if (!(s > 0) || !std::isfinite(s)) return fail(MPDE_ERR_INVALID_ARG, "steps must be finite and > 0");
+      N *= n;
+    }
+    if (N > (1LL << 30)) return fail(MPDE_ERR_UNSUPPORTED, "instance too large (> 2^30 points)");
+  }
+  if (d->opts) opt = *d->opts; else mpde_default_options(&opt);
+  if (!(opt.tol > 0) || opt.max_outer < 0 || opt.max_inner < 1 || opt.nu < 1 || opt.nu > 16 || opt.coarse_min < 4 ||
+      opt.max_levels < 1 || opt.inner_tol < 0 || opt.inner_tol >= 1)
+    return fail(MPDE_ERR_INVALID_ARG, "invalid options");
+  return MPDE_OK;
+}
+
+// Level plan of one instance: halve spatial axes (a >= 1) while even and at
+// or above the minimum (periodic: coarse_min, else 5); time stays.
+void plan(const int* n0, const double* s0, int D, const int* per, const mpde_options& opt,
+          std::vector<std::array<int, 3>>& shapes, std::vector<std::array<double, 3>>& steps,
+          std::vector<std::array<int, 3>>& halv) {
+  std::array<int, 3> n{1, 1, 1}, k{0, 0, 0};
+  std::array<double, 3> s{1, 1, 1};
+  for (int a = 0; a < D; ++a) { n[a] = n0[a]; s[a] = s0[a]; }
+  shapes = {n}; steps = {s}; halv = {k};
+  while ((int)shapes.size() < opt.max_levels) {
+    bool any = false;
+    for (int a = 1; a < D; ++a) {
+      const int lim = per[a] ? opt.coarse_min : 5;
+      if (n[a] % 2 == 0 && n[a] / 2 >= lim) { n[a] /= 2; s[a] *= 2; k[a] += 1; any = true; }
+    }
+    if (!any) break;
+    shapes.push_back(n); steps.push_back(s); halv.push_back(k);
+  }
+}
+
+template <typename TV, typename TC>
+void build_impl(mpde_problem* P, const mpde_desc* d) {
+  Solver<TV, TC> S(P);
+  hipStream_t st = P->st;
+  const int B = P->B, D = P->D;
+  int per[3] = {0, 0, 0};
+  for (int a = 0; a < D; ++a) per[a] = d->bc_lo[a] == MPDE_BC_PERIODIC;
+  // plan
+  std::vector<std::vector<std::array<double, 3>>> lsteps(B);
+  std::vector<std::vector<std::array<int, 3>>> lhalv(B);
+  P->lshape.resize(B);
+  P->nlev.resize(B);
+  int maxl = 0;
+  for (int b = 0; b < B; ++b) {
+    plan(d->shape + b * D, d->step + b * D, D, per, P->opt, P->lshape[b], lsteps[b], lhalv[b]);
+    P->nlev[b] = (int)P->lshape[b].size();
+    maxl = std::max(maxl, P->nlev[b]);
+    long long Nc = 1;
+    for (int a = 0; a < D; ++a) Nc *= P->lshape[b].back()[a];
+    if (Nc > kMaxDense)
+      throw std::string("coarsest grid of instance " + std::to_string(b) + " has " + std::to_string(Nc) +
+                        " points; the dense coarsest solve supports at most " + std::to_string(kMaxDense) +
+                        " (time axis too long or spatial axes not halvable)");
+  }
+  P->lv.resize(maxl);
+  for (int l = 0; l < maxl; ++l) {
+    Level& L = P->lv[l];
+    L.h.assign(B, LInst{});
+    long long off = 0;
+    std::vector<int> sel_all(B, 0), sel_smooth(B, 0), sel_dense(B, 0);
+    for (int b = 0; b < B; ++b) {
+      LInst& q = L.h[b];
+      std::memset(&q, 0, sizeof(q));
+      for (int a = 0; a < 3; ++a) { q.n[a] = 1; q.wT[a] = q.wC1[a] = q.wC2[a] = 1.0; q.s[a] = 1; q.is1[a] = q.is2[a] = 1; }
+      if (l >= P->nlev[b]) continue;
+      long long N = 1;
+      for (int a = 0; a < D; ++a) {
+        q.n[a] = P->lshape[b][l][a];
+        q.s[a] = lsteps[b][l][a];
+        q.is1[a] = 1.0 / q.s[a];
+        q.is2[a] = 1.0 / (q.s[a] * q.s[a]);
+        q.per[a] = per[a];
+        q.dlo[a] = d->bc_lo[a] == MPDE_BC_DIRICHLET;
+        q.dhi[a] = d->bc_hi[a] == MPDE_BC_DIRICHLET;
+        const int k = lhalv[b][l][a];
+        q.wT[a] = std::ldexp(1.0, -k);
+        q.wC1[a] = std::ldexp(1.0, -k);
+        q.wC2[a] = std::ldexp(1.0, -2 * k);
+        N *= q.n[a];
+      }
+      int st_ = 1;
+      for (int a = D - 1; a >= 0; --a) { q.str[a] = st_; st_ *= q.n[a]; }
+      q.N = (int)N;
+      q.coarsest = (l == P->nlev[b] - 1);
+      q.ncoarsened = 0;
+      if (l > 0)
+        for (int a = 0; a < D; ++a) q.ncoarsened += (P->lshape[b][l][a] != P->lshape[b][l - 1][a]);
+      q.cheb_theta = 2.2; q.cheb_delta = 1.8;
+      q.voff = off;
+      q.coff = off * P->K;
+      off += N;
+      sel_all[b] = 1;
+      sel_smooth[b] = !q.coarsest;
+      sel_dense[b] = q.coarsest;
+    }
+    L.npts = off;
+    make_table(L.all, L.h, B, sel_all);
+    make_table(L.smooth, L.h, B, sel_smooth);
+    make_table(L.dense, L.h, B, sel_dense);
+  }
+  // device structures
+  size_t maxnb = 1;
+  for (auto& L : P->lv) {
+    L.d = P->alloc<LInst>(B);
+    HIPCHK(hipMemcpy(L.d, L.h.data(), B * sizeof(LInst), hipMemcpyHostToDevice));
+    upload_table(P, L.all); upload_table(P, L.smooth); upload_table(P, L.dense);
+    maxnb = std::max(maxnb, L.all.h.size());
+  }
+  S.alloc_vectors();
+  const long long n0 = P->lv[0].npts;
+  P->partial = P->alloc<double>(maxnb);
+  for (double** a : {&P->rz_new, &P->rz, &P->beta, &P->pq, &P->alpha, &P->rn2, &P->r0n2, &P->atd2, &P->scale, &P->iscale})
+    *a = P->alloc<double>(B);
+  P->active = P->alloc<int>(B);
+  P->iters = P->alloc<int>(B);
+  P->flag = P->alloc<int>(1);
+  P->u64 = P->alloc<double>(n0);
+  P->du64 = P->alloc<double>(n0);
+  P->r64 = P->alloc<double>(n0);
+  P->g64 = P->alloc<double>(n0);
+  P->ghat = P->alloc<double>(n0);
+  P->vloc = P->alloc<double>((size_t)2 * D * n0);
+  P->zoff_h.resize(B);
+  for (int b = 0; b < B; ++b) P->zoff_h[b] = (long long)P->V * P->lv[0].h[b].voff;
+  P->zoff = P->alloc<long long>(B);
+  HIPCHK(hipMemcpy(P->zoff, P->zoff_h.data(), B * sizeof(long long), hipMemcpyHostToDevice));
+  // inputs (caller's device memory, same concatenated layout as level 0)
+  HIPCHK(hipMemcpyAsync(P->lv[0].coef, d->coeff, (size_t)P->K * n0 * sizeof(TC), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(P->f, d->rhs, n0 * sizeof(TC), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(P->w, d->bc_values, n0 * sizeof(TC), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemsetAsync(P->flag, 0, sizeof(int), st));
+  launch_nonfinite<TC>(st, (const TC*)P->lv[0].coef, (long long)P->K * n0, P->flag);
+  launch_nonfinite<TC>(st, (const TC*)P->f, n0, P->flag);
+  launch_nonfinite<TC>(st, (const TC*)P->w, n0, P->flag);
+  int hflag = 0;
+  HIPCHK(hipMemcpyAsync(&hflag, P->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (hflag) throw 1;   // non-finite input
+  S.coarsen_all();
+  S.setup_level_operators();
+  S.build_dense();
+  S.atd_norm();
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+template <typename TV, typename TC>
+int solve_impl(mpde_problem* P, void* z_out, mpde_info* info) {
+  Solver<TV, TC> S(P);
+  const int code = S.refine(false, P->u64, P->atd2, info);
+  S.template output<TC>((TC*)z_out);
+  HIPCHK(hipStreamSynchronize(P->st));
+  P->has_solution = true;
+  return code;
+}
+
+template <typename TV, typename TC>
+int adjoint_impl(mpde_problem* P, const void* gz, void* gc, void* gf, void* gw, mpde_info* info) {
+  Solver<TV, TC> S(P);
+  return S.template adjoint<TC>((const TC*)gz, (TC*)gc, (TC*)gf, (TC*)gw, info);
+}
+
+int hip_fail(const HipError& h) {
+  const int code = (h.e == hipErrorOutOfMemory || h.e == hipErrorMemoryAllocation) ? MPDE_ERR_OUT_OF_MEMORY : MPDE_ERR_HIP;
+  return fail(code, std::string("HIP error in ") + h.what + ": " + hipGetErrorString(h.e));
+}
+
+bool g_stencils_ready = false;
+
+int ensure_device() {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return fail(MPDE_ERR_NO_DEVICE, "no HIP device available");
+  if (!g_stencils_ready) {
+    double w1[5][5], w2[5][5];
+    fd_table(1, w1);
+    fd_table(2, w2);
+    if (upload_stencils(w1, w2) != hipSuccess) return fail(MPDE_ERR_HIP, "failed to upload stencil weights");
+    g_stencils_ready = true;
+  }
+  return MPDE_OK;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+int mpde_default_options(mpde_options* o) {
+  if (!o) return fail(MPDE_ERR_INVALID_ARG, "options pointer is NULL");
+  std::memset(o, 0, sizeof(*o));
+  o->tol = 1e-6;
+  o->inner_tol = 0.0;
+  o->max_outer = 30;
+  o->max_inner = 200;
+  o->nu = 2;
+  o->coarse_min = 4;
+  o->check_every = 2;
+  o->max_levels = 16;
+  return MPDE_OK;
+}
+
+const char* mpde_last_error(void) { return g_err.c_str(); }
+
+int mpde_build(const mpde_desc* d, mpde_problem** out) {
+  g_err.clear();
+  if (!out) return fail(MPDE_ERR_INVALID_ARG, "out pointer is NULL");
+  *out = nullptr;
+  mpde_options opt;
+  int rc = validate(d, opt);
+  if (rc) return rc;
+  rc = ensure_device();
+  if (rc) return rc;
+  mpde_problem* P = new (std::nothrow) mpde_problem();
+  if (!P) return fail(MPDE_ERR_OUT_OF_MEMORY, "host allocation failed");
+  P->dtype = d->dtype; P->D = d->ndim; P->B = d->batch; P->V = 1 + 2 * d->ndim;
+  P->mset = d->mset; P->opt = opt; P->st = (hipStream_t)d->stream;
+  for (int a = 0; a < 3; ++a) { P->bc_lo[a] = d->bc_lo[a]; P->bc_hi[a] = d->bc_hi[a]; }
+  int K = 0;
+  for (int v = 0; v < 1 + 2 * kMaxD; ++v) P->ci.k[v] = -1;
+  for (int v = 0; v < P->V; ++v)
+    if (d->mset >> v & 1u) P->ci.k[v] = K++;
+  P->ci.K = K; P->K = K;
+  try {
+    if (P->dtype == MPDE_F32) build_impl<float, float>(P, d);
+    else build_impl<double, double>(P, d);
+  } catch (const HipError& h) {
+    delete P;
+    return hip_fail(h);
+  } catch (const std::string& m) {
+    delete P;
+    return fail(MPDE_ERR_UNSUPPORTED, m);
+  } catch (int) {
+    delete P;
+    return fail(MPDE_ERR_NONFINITE, "non-finite value in coeff, rhs or bc_values");
+  } catch (const std::bad_alloc&) {
+    delete P;
+    return fail(MPDE_ERR_OUT_OF_MEMORY, "host allocation failed");
+  }
+  *out = P;
+  return MPDE_OK;
+}
+
+int mpde_solve(mpde_problem* p, void* z_out, mpde_info* info) {
+  g_err.clear();
+  if (!p) return fail(MPDE_ERR_INVALID_ARG, "problem handle is NULL");
+  if (!z_out) return fail(MPDE_ERR_INVALID_ARG, "z_out is NULL");
+  auto t0 = std::chrono::steady_clock::now();
+  int rc;
+  try {
+    rc = p->dtype == MPDE_F32 ? solve_impl<float, float>(p, z_out, info) : solve_impl<double, double>(p, z_out, info);
+  } catch (const HipError& h) {
+    return hip_fail(h);
+  }
+  if (info) info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (rc == MPDE_WARN_NOT_CONVERGED) g_err = "at least one instance did not reach the tolerance";
+  return rc;
+}
+
+int mpde_solve_adjoint(mpde_problem* p, const void* g_z, void* grad_coeff, void* grad_rhs, void* grad_bc,
+                       mpde_info* info) {
+  g_err.clear();
+  if (!p) return fail(MPDE_ERR_INVALID_ARG, "problem handle is NULL");
+  if (!g_z) return fail(MPDE_ERR_INVALID_ARG, "g_z is NULL");
+  if (!p->has_solution) return fail(MPDE_ERR_BAD_STATE, "mpde_solve must succeed before mpde_solve_adjoint");
+  auto t0 = std::chrono::steady_clock::now();
+  int rc;
+  try {
+    rc = p->dtype == MPDE_F32 ? adjoint_impl<float, float>(p, g_z, grad_coeff, grad_rhs, grad_bc, info)
+                              : adjoint_impl<double, double>(p, g_z, grad_coeff, grad_rhs, grad_bc, info);
+  } catch (const HipError& h) {
+    return hip_fail(h);
+  }
+  if (info) info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (rc == MPDE_WARN_NOT_CONVERGED) g_err = "at least one instance did not reach the tolerance";
+  return rc;
+}
+
+
+void mpde_free(mpde_problem* p) { delete p; }
+
+int mpde_levels(const mpde_problem* p, int32_t b, int32_t* shapes) {
+  if (!p || b < 0 || b >= p->B) return 0;
+  const int nl = p->nlev[b];
+  if (shapes)
+    for (int l = 0; l < nl; ++l)
+      for (int a = 0; a < p->D; ++a) shapes[l * p->D + a] = p->lshape[b][l][a];
+  return nl;
+}
+
+}  // extern "C"

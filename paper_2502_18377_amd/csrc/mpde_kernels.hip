@@ -1,0 +1,1256 @@
+// HIP kernels (gfx950) of the NeuRLP-PDE solver: the matrix-free reduced
+// normal-equation operator, Chebyshev smoothing, grid transfers, the dense
+// coarsest-grid solve, Krylov reductions and vector updates, the output of
+// all derivative unknowns, and the backward-pass kernels.
+//
+// Every kernel is thread-per-grid-point over a table of (instance, first
+// point) work items, so uniform and ragged batches share one launch per
+// stage; blocks never straddle two instances, which keeps every per-instance
+// reduction in a fixed order (two-stage, no floating-point atomics).
+#include "mpde_internal.hpp"
+#include "mpde_kernels.hpp"
+
+namespace mpde {
+
+// 5-point difference weights, [window position][k], window offsets
+// k - position; filled by the host from the moment conditions (Eq. 5).
+__constant__ double c_W1[5][5];
+__constant__ double c_W2[5][5];
+__constant__ float c_W1f[5][5];
+__constant__ float c_W2f[5][5];
+
+hipError_t upload_stencils(const double w1[5][5], const double w2[5][5]) {
+  float f1[5][5], f2[5][5];
+  for (int i = 0; i < 5; ++i)
+    for (int k = 0; k < 5; ++k) { f1[i][k] = (float)w1[i][k]; f2[i][k] = (float)w2[i][k]; }
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_W1), w1, sizeof(double) * 25);
+  if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_W2), w2, sizeof(double) * 25);
+  if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_W1f), f1, sizeof(float) * 25);
+  if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_W2f), f2, sizeof(float) * 25);
+  return e;
+}
+
+template <typename TA> __device__ __forceinline__ TA W1(int p, int k);
+template <typename TA> __device__ __forceinline__ TA W2(int p, int k);
+template <> __device__ __forceinline__ float W1<float>(int p, int k) { return c_W1f[p][k]; }
+template <> __device__ __forceinline__ float W2<float>(int p, int k) { return c_W2f[p][k]; }
+template <> __device__ __forceinline__ double W1<double>(int p, int k) { return c_W1[p][k]; }
+template <> __device__ __forceinline__ double W2<double>(int p, int k) { return c_W2[p][k]; }
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ void axis_class(int i, int n, int per, int& tp, int& tm, int& wp) {
+  if (per) { tp = 1; tm = 1; wp = 2; return; }
+  tp = (i + 1 < n);
+  tm = (i >= 1);
+  int st = i - 2;
+  st = st < 0 ? 0 : st;
+  st = st > n - 5 ? n - 5 : st;
+  wp = i - st;
+}
+
+// Flat index of the point o steps from p along an axis (wrapping if periodic).
+__device__ __forceinline__ long long nbr(long long p, int ia, int o, int n, int str, int per) {
+  int j = ia + o;
+  if (per) { if (j < 0) j += n; else if (j >= n) j -= n; }
+  return p + (long long)(j - ia) * str;
+}
+
+template <int D>
+__device__ __forceinline__ void coords(const LInst& L, int p, int* c) {
+  if (D == 2) { c[0] = p / L.n[1]; c[1] = p - c[0] * L.n[1]; }
+  else { int q = p / L.n[2]; c[2] = p - q * L.n[2]; c[0] = q / L.n[1]; c[1] = q - c[0] * L.n[1]; }
+}
+
+template <typename TC>
+__device__ __forceinline__ double coef(const TC* c, const LInst& L, int k, long long p) {
+  return k < 0 ? 0.0 : (double)c[L.coff + (long long)k * L.N + p];
+}
+
+// Row residuals of axis a at point (p, ia) for field u (weighted), plus the
+// class of the point on that axis.  u values at the 5-point window are loaded
+// once; the Taylor neighbours are window[wp-1] and window[wp+1].
+template <typename TA, typename TV>
+struct AxisRows {
+  TA rTp, rTm, rC1, rC2;
+  int tp, tm, wp;
+};
+
+template <typename TA, typename TV>
+__device__ __forceinline__ AxisRows<TA, TV> axis_rows(const LInst& L, int a, const TV* u,
+                                                      long long p, int ia, TA ui) {
+  AxisRows<TA, TV> R;
+  const int n = L.n[a], st = L.str[a], per = L.per[a];
+  axis_class(ia, n, per, R.tp, R.tm, R.wp);
+  TA w[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    int o = k - R.wp;
+    w[k] = (o == 0) ? ui : (TA)u[nbr(p, ia, o, n, st, per)];
+  }
+  TA s1 = 0, s2 = 0;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    s1 += W1<TA>(R.wp, k) * w[k];
+    s2 += W2<TA>(R.wp, k) * w[k];
+  }
+  const TA wT = (TA)L.wT[a];
+  TA up = (R.wp < 4) ? w[R.wp + 1] : (TA)0;
+  TA um = (R.wp > 0) ? w[R.wp - 1] : (TA)0;
+  R.rTp = R.tp ? wT * (ui - up) : (TA)0;
+  R.rTm = R.tm ? wT * (ui - um) : (TA)0;
+  R.rC1 = -(TA)L.wC1[a] * s1;
+  R.rC2 = -(TA)L.wC2[a] * s2;
+  return R;
+}
+
+// 2x2 inverse of the per-axis Gram block G_a (depends on tp, tm and weights).
+template <typename TA>
+__device__ __forceinline__ void ginv(const LInst& L, int a, int tp, int tm, TA& i11, TA& i12, TA& i22) {
+  const TA wT2 = (TA)(L.wT[a] * L.wT[a]);
+  const TA t = (TA)(tp + tm), dlt = (TA)(tp - tm);
+  const TA g11 = wT2 * t + (TA)(L.wC1[a] * L.wC1[a]);
+  const TA g12 = wT2 * dlt * (TA)0.5;
+  const TA g22 = wT2 * t * (TA)0.25 + (TA)(L.wC2[a] * L.wC2[a]);
+  const TA inv = (TA)1 / (g11 * g22 - g12 * g12);
+  i11 = g22 * inv; i12 = -g12 * inv; i22 = g11 * inv;
+}
+
+// Scaled equation-row coefficients of axis a's derivative unknowns at p.
+template <typename TA, typename TC>
+__device__ __forceinline__ void chat(const LInst& L, const CIdx& ci, const TC* c, int a, long long p,
+                                     TA& ca, TA& caa) {
+  const int k1 = ci.k[1 + 2 * a], k2 = ci.k[2 + 2 * a];
+  ca = k1 < 0 ? (TA)0 : (TA)c[L.coff + (long long)k1 * L.N + p] * (TA)L.is1[a];
+  caa = k2 < 0 ? (TA)0 : (TA)c[L.coff + (long long)k2 * L.N + p] * (TA)L.is2[a];
+}
+
+// gamma at point p: the projected equation-row residual (see header).
+template <int D, typename TA, typename TV, typename TC>
+__device__ __forceinline__ TA gamma_at(const LInst& L, const CIdx& ci, const TV* u, const TC* c,
+                                       const TC* f, int sigma, long long p, const int* ic) {
+  const TA ui = (TA)u[L.voff + p];
+  TA rhoE = (ci.k[0] < 0 ? (TA)0 : (TA)c[L.coff + (long long)ci.k[0] * L.N + p]) * ui;
+  if (sigma) rhoE -= (TA)f[L.voff + p];
+  TA kappa = 1, num = rhoE;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    AxisRows<TA, TV> R = axis_rows<TA, TV>(L, a, u + L.voff, p, ic[a], ui);
+    TA i11, i12, i22;
+    ginv<TA>(L, a, R.tp, R.tm, i11, i12, i22);
+    const TA wT = (TA)L.wT[a];
+    const TA b1 = wT * (R.rTp - R.rTm) + (TA)L.wC1[a] * R.rC1;
+    const TA b2 = wT * (R.rTp + R.rTm) * (TA)0.5 + (TA)L.wC2[a] * R.rC2;
+    const TA g1 = i11 * b1 + i12 * b2, g2 = i12 * b1 + i22 * b2;
+    TA ca, caa;
+    chat<TA, TC>(L, ci, c, a, p, ca, caa);
+    const TA h1 = i11 * ca + i12 * caa, h2 = i12 * ca + i22 * caa;
+    kappa += ca * h1 + caa * h2;
+    num -= ca * g1 + caa * g2;
+  }
+  return num / kappa;
+}
+
+// Projected axis-a rows q = rho + A_w,a x* at point (pi, ia) given gamma_i.
+template <typename TA, typename TV, typename TC>
+__device__ __forceinline__ void q_axis(const LInst& L, const CIdx& ci, const TV* u, const TC* c,
+                                       const TV* gam, int a, long long pi, int ia, TA& qTp, TA& qTm,
+                                       TA& qC1, TA& qC2, int& tp, int& tm, int& wp) {
+  const TA ui = (TA)u[pi];
+  AxisRows<TA, TV> R = axis_rows<TA, TV>(L, a, u, pi, ia, ui);
+  tp = R.tp; tm = R.tm; wp = R.wp;
+  TA i11, i12, i22;
+  ginv<TA>(L, a, R.tp, R.tm, i11, i12, i22);
+  const TA wT = (TA)L.wT[a];
+  const TA b1 = wT * (R.rTp - R.rTm) + (TA)L.wC1[a] * R.rC1;
+  const TA b2 = wT * (R.rTp + R.rTm) * (TA)0.5 + (TA)L.wC2[a] * R.rC2;
+  TA ca, caa;
+  chat<TA, TC>(L, ci, c, a, pi, ca, caa);
+  const TA g = (TA)gam[pi];
+  const TA x1 = -(i11 * (b1 + ca * g) + i12 * (b2 + caa * g));
+  const TA x2 = -(i12 * (b1 + ca * g) + i22 * (b2 + caa * g));
+  qTp = R.tp ? R.rTp + wT * (x1 + (TA)0.5 * x2) : (TA)0;
+  qTm = R.tm ? R.rTm + wT * (-x1 + (TA)0.5 * x2) : (TA)0;
+  qC1 = R.rC1 + (TA)L.wC1[a] * x1;
+  qC2 = R.rC2 + (TA)L.wC2[a] * x2;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Fixed-order block sum (256 threads = 4 waves); result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double part[kBlock / 64];
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) part[wid] = v;
+  __syncthreads();
+  double s = 0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) s += part[w];
+  }
+  __syncthreads();
+  return s;
+}
+
+// ---------------------------------------------------------------- kernels
+template <int D, typename TA, typename TV, typename TC>
+__global__ void __launch_bounds__(kBlock) k_gamma(const Work* __restrict__ work, const LInst* __restrict__ li,
+                                                  CIdx ci, const TV* __restrict__ u, const TC* __restrict__ c,
+                                                  const TC* __restrict__ f, int sigma, TV* __restrict__ gam) {
+  const Work w = work[blockIdx.x];
+  const LInst& L = li[w.inst];
+  const int p = w.start + threadIdx.x;
+  if (p >= L.N) return;
+  int ic[kMaxD];
+  coords<D>(L, p, ic);
+  gam[L.voff + p] = (TV)gamma_at<D, TA, TV, TC>(L, ci, u, c, f, sigma, p, ic);
+}
+
+// y_j = (A_u^T Pi (A_u u - sigma d))_j, then the epilogue of `mode`.
+template <int D, typename TA, typename TV, typename TC>
+__global__ void __launch_bounds__(kBlock) k_gather(const Work* __restrict__ work, const LInst* __restrict__ li,
+                                                   CIdx ci, const TV* __restrict__ u, const TV* __restrict__ gam,
+                                                   const TC* __restrict__ c, const TC* __restrict__ w,
+                                                   int sigma, int mode, TV* __restrict__ out,
+                                                   const TV* __restrict__ bvec, TV* __restrict__ xv,
+                                                   TV* __restrict__ rv, TV* __restrict__ dv,
+                                                   const TV* __restrict__ dinv, int cheb_step,
+                                                   double* __restrict__ partial) {
+  const Work wk = work[blockIdx.x];
+  const LInst& L = li[wk.inst];
+  const int j = wk.start + threadIdx.x;
+  const bool live = j < L.N;
+  TA y = 0, uj = 0;
+  if (live) {
+    int ic[kMaxD];
+    coords<D>(L, j, ic);
+    const TV* U = u + L.voff;
+    const TV* G = gam + L.voff;
+    uj = (TA)U[j];
+    y = (ci.k[0] < 0 ? (TA)0 : (TA)c[L.coff + (long long)ci.k[0] * L.N + j]) * (TA)G[j];  // equation row (q_E = gamma)
+    bool onB = false;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+      onB |= (L.dlo[a] && ic[a] == 0) || (L.dhi[a] && ic[a] == L.n[a] - 1);
+    if (onB) y += uj - (sigma ? (TA)w[L.voff + j] : (TA)0);  // boundary row
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int n = L.n[a], st = L.str[a], per = L.per[a], ia = ic[a];
+      const TA wT = (TA)L.wT[a], wC1 = (TA)L.wC1[a], wC2 = (TA)L.wC2[a];
+      const int R = per ? 2 : 4;
+      for (int o = -R; o <= R; ++o) {       // candidate row owner i = j + o e_a
+        const int ii = ia + o;
+        if (!per && (ii < 0 || ii >= n)) continue;
+        const int iw = per ? ((ii % n) + n) % n : ii;
+        int tp, tm, wp;
+        axis_class(iw, n, per, tp, tm, wp);
+        const int k = wp - o;               // position of j in row i's window
+        const bool inC = (k >= 0 && k <= 4);
+        const bool inT = (o >= -1 && o <= 1);
+        if (!inC && !inT) continue;
+        const long long pi = nbr(j, ia, o, n, st, per);
+        TA qTp, qTm, qC1, qC2;
+        q_axis<TA, TV, TC>(L, ci, U, c, G, a, pi, iw, qTp, qTm, qC1, qC2, tp, tm, wp);
+        if (inC) y -= wC1 * W1<TA>(wp, k) * qC1 + wC2 * W2<TA>(wp, k) * qC2;
+        if (o == 0) y += wT * (qTp + qTm);
+        else if (o == -1) y -= wT * qTp;    // T+ of j - e_a ends at j
+        else if (o == 1) y -= wT * qTm;     // T- of j + e_a ends at j
+      }
+    }
+  }
+  const long long gj = L.voff + j;
+  if (mode == G_STORE) {
+    if (live) out[gj] = (TV)y;
+  } else if (mode == G_RESID) {
+    if (live) {
+      TA r = (bvec ? (TA)bvec[gj] : (TA)0) - y;
+      out[gj] = (TV)r;
+      if (dv) dv[gj] = (TV)((TA)dinv[gj] * r / (TA)L.cheb_theta);
+    }
+  } else if (mode == G_CHEB) {
+    if (live) {
+      // Chebyshev recurrence on [lo, hi] of D^-1 S: rho_0 = 1/sigma1,
+      // rho_k = 1/(2 sigma1 - rho_{k-1}); d_k = rho_k rho_{k-1} d + 2 rho_k/delta D^-1 r.
+      const double th = L.cheb_theta, de = L.cheb_delta, s1 = th / de;
+      double rp = 1.0 / s1, rn = 0;
+      for (int s = 0; s <= cheb_step; ++s) { rn = 1.0 / (2.0 * s1 - rp); if (s < cheb_step) rp = rn; }
+      const TA d = uj;
+      xv[gj] = (TV)((TA)xv[gj] + d);
+      const TA r = (TA)rv[gj] - y;
+      rv[gj] = (TV)r;
+      dv[gj] = (TV)((TA)(rn * rp) * d + (TA)(2.0 * rn / de) * (TA)dinv[gj] * r);
+    }
+  } else {  // G_STORE_DOT
+    if (live) out[gj] = (TV)y;
+    double s = block_sum(live ? (double)uj * (double)y : 0.0);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  }
+}
+
+// Diagonal of S (inverse stored): sum over the rows touching u_j of a^T Pi a.
+template <int D, typename TV, typename TC>
+__global__ void __launch_bounds__(kBlock) k_diag(const Work* __restrict__ work, const LInst* __restrict__ li,
+                                                 CIdx ci, const TC* __restrict__ c, TV* __restrict__ dinv) {
+  const Work wk = work[blockIdx.x];
+  const LInst& L = li[wk.inst];
+  const int j = wk.start + threadIdx.x;
+  if (j >= L.N) return;
+  int ic[kMaxD];
+  coords<D>(L, j, ic);
+  double diag = 0;
+  bool onB = false;
+  for (int a = 0; a < D; ++a) onB |= (L.dlo[a] && ic[a] == 0) || (L.dhi[a] && ic[a] == L.n[a] - 1);
+  if (onB) diag += 1.0;
+  // Per-point quantities of a row owner i: kappa_i, h_b(i) for all axes.
+  auto kappa_at = [&](long long pi, const int* ii) {
+    double kap = 1;
+    for (int b = 0; b < D; ++b) {
+      int tp, tm, wp;
+      axis_class(ii[b], L.n[b], L.per[b], tp, tm, wp);
+      double i11, i12, i22, ca, caa;
+      ginv<double>(L, b, tp, tm, i11, i12, i22);
+      chat<double, TC>(L, ci, c, b, pi, ca, caa);
+      kap += ca * (i11 * ca + i12 * caa) + caa * (i12 * ca + i22 * caa);
+    }
+    return kap;
+  };
+  // Self rows (owner i = j): all axes plus the equation row.
+  {
+    double rhoE = coef(c, L, ci.k[0], j), num = rhoE, kap = 1;
+    double ra[kMaxD][4], g1[kMaxD], g2[kMaxD], h1[kMaxD], h2[kMaxD];
+    for (int a = 0; a < D; ++a) {
+      int tp, tm, wp;
+      axis_class(ic[a], L.n[a], L.per[a], tp, tm, wp);
+      double wT = L.wT[a];
+      ra[a][0] = tp ? wT : 0; ra[a][1] = tm ? wT : 0;
+      ra[a][2] = -L.wC1[a] * c_W1[wp][wp]; ra[a][3] = -L.wC2[a] * c_W2[wp][wp];
+      double i11, i12, i22, ca, caa;
+      ginv<double>(L, a, tp, tm, i11, i12, i22);
+      double b1 = wT * (ra[a][0] - ra[a][1]) + L.wC1[a] * ra[a][2];
+      double b2 = wT * (ra[a][0] + ra[a][1]) * 0.5 + L.wC2[a] * ra[a][3];
+      g1[a] = i11 * b1 + i12 * b2; g2[a] = i12 * b1 + i22 * b2;
+      chat<double, TC>(L, ci, c, a, j, ca, caa);
+      h1[a] = i11 * ca + i12 * caa; h2[a] = i12 * ca + i22 * caa;
+      kap += ca * h1[a] + caa * h2[a];
+      num -= ca * g1[a] + caa * g2[a];
+    }
+    double gam = num / kap;
+    diag += rhoE * gam;
+    for (int a = 0; a < D; ++a) {
+      double wT = L.wT[a];
+      double x1 = -(g1[a] + h1[a] * gam), x2 = -(g2[a] + h2[a] * gam);
+      double q0 = ra[a][0] != 0 ? ra[a][0] + wT * (x1 + 0.5 * x2) : 0;
+      double q1 = ra[a][1] != 0 ? ra[a][1] + wT * (-x1 + 0.5 * x2) : 0;
+      double q2 = ra[a][2] + L.wC1[a] * x1, q3 = ra[a][3] + L.wC2[a] * x2;
+      diag += ra[a][0] * q0 + ra[a][1] * q1 + ra[a][2] * q2 + ra[a][3] * q3;
+    }
+  }
+  // Rows of other owners along each axis.
+  for (int a = 0; a < D; ++a) {
+    const int n = L.n[a], per = L.per[a], ia = ic[a];
+    const int R = per ? 2 : 4;
+    for (int o = -R; o <= R; ++o) {
+      if (o == 0) continue;
+      const int ii = ia + o;
+      if (!per && (ii < 0 || ii >= n)) continue;
+      const int iw = per ? ((ii % n) + n) % n : ii;
+      if (per && n == 4 && o == -2) continue;      // same owner as o = +2, merged below
+      int tp, tm, wp;
+      axis_class(iw, n, per, tp, tm, wp);
+      double a4[4] = {0, 0, 0, 0};
+      int k = wp - o;
+      if (k >= 0 && k <= 4) { a4[2] = -L.wC1[a] * c_W1[wp][k]; a4[3] = -L.wC2[a] * c_W2[wp][k]; }
+      if (per && n == 4 && o == 2) {               // the o = -2 window entry of the same owner
+        int k2 = wp + 2;
+        a4[2] += -L.wC1[a] * c_W1[wp][k2]; a4[3] += -L.wC2[a] * c_W2[wp][k2];
+      }
+      if (o == -1 && tp) a4[0] = -L.wT[a];
+      if (o == 1 && tm) a4[1] = -L.wT[a];
+      if (a4[0] == 0 && a4[1] == 0 && a4[2] == 0 && a4[3] == 0) continue;
+      const long long pi = nbr(j, ia, o, n, L.str[a], per);
+      int ii3[kMaxD];
+      for (int b = 0; b < D; ++b) ii3[b] = ic[b];
+      ii3[a] = iw;
+      double kap = kappa_at(pi, ii3);
+      double i11, i12, i22, ca, caa;
+      ginv<double>(L, a, tp, tm, i11, i12, i22);
+      double wT = L.wT[a];
+      double b1 = wT * (a4[0] - a4[1]) + L.wC1[a] * a4[2];
+      double b2 = wT * (a4[0] + a4[1]) * 0.5 + L.wC2[a] * a4[3];
+      double g1 = i11 * b1 + i12 * b2, g2 = i12 * b1 + i22 * b2;
+      chat<double, TC>(L, ci, c, a, pi, ca, caa);
+      double h1 = i11 * ca + i12 * caa, h2 = i12 * ca + i22 * caa;
+      double gam = -(ca * g1 + caa * g2) / kap;
+      double x1 = -(g1 + h1 * gam), x2 = -(g2 + h2 * gam);
+      double q0 = tp ? a4[0] + wT * (x1 + 0.5 * x2) : 0;
+      double q1 = tm ? a4[1] + wT * (-x1 + 0.5 * x2) : 0;
+      double q2 = a4[2] + L.wC1[a] * x1, q3 = a4[3] + L.wC2[a] * x2;
+      diag += a4[0] * q0 + a4[1] * q1 + a4[2] * q2 + a4[3] * q3;
+    }
+  }
+  dinv[L.voff + j] = (TV)(1.0 / diag);
+}
+
+// Chebyshev start from x = 0: x = 0, r = b, d = D^-1 b / theta.
+template <typename TV>
+__global__ void __launch_bounds__(kBlock) k_cheb_init(const Work* __restrict__ work, const LInst* __restrict__ li,
+                                                      const TV* __restrict__ b, const TV* __restrict__ dinv,
+                                                      TV* __restrict__ x, TV* __restrict__ r, TV* __restrict__ d) {
+  const Work wk = work[blockIdx.x];
+  const LInst& L = li[wk.inst];
+  const int j = wk.start + threadIdx.x;
+  if (j >= L.N) return;
+  const long long g = L.voff + j;
+  const TV bb = b[g];
+  x[g] = (TV)0;
+  r[g] = bb;
+  d[g] = (TV)((double)dinv[g] * (double)bb / L.cheb_theta);
+}
+
+// Restriction r_c = P^T r_f / 2^(coarsened axes) over coarse points; P is
+// linear interpolation along the halved (spatial) axes.
+template <int D, typename TV>
+__global__ void __launch_bounds__(kBlock) k_restrict(const Work* __restrict__ work, const LInst* __restrict__ lf,
+                                                     const LInst* __restrict__ lc, const TV* __restrict__ rf,
+                                                     TV* __restrict__ rc) {
+  const Work wk = work[blockIdx.x];
+  const LInst& C = lc[wk.inst];
+  const LInst& F = lf[wk.inst];
+  const int jc = wk.start + threadIdx.x;
+  if (jc >= C.N) return;
+  int cc[kMaxD];
+  coords<D>(C, jc, cc);
+  int fi[kMaxD][3];
+  double fw[kMaxD][3];
+  int cnt[kMaxD];
+  for (int a = 0; a < D; ++a) {
+    if (C.n[a] == F.n[a]) { cnt[a] = 1; fi[a][0] = cc[a]; fw[a][0] = 1; continue; }
+    const int nf = F.n[a], ncn = C.n[a], X = cc[a];
+    int m = 0;
+    fi[a][m] = 2 * X; fw[a][m++] = 1.0;
+    if (F.per[a]) {
+      fi[a][m] = (2 * X - 1 + nf) % nf; fw[a][m++] = 0.5;
+      fi[a][m] = (2 * X + 1) % nf; fw[a][m++] = 0.5;
+    } else {
+      if (X >= 1) { fi[a][m] = 2 * X - 1; fw[a][m++] = 0.5; }
+      if (2 * X + 1 < nf) { fi[a][m] = 2 * X + 1; fw[a][m++] = (X + 1 < ncn) ? 0.5 : 1.0; }
+    }
+    cnt[a] = m;
+  }
+  double acc = 0;
+  int idx[kMaxD] = {0, 0, 0};
+  const int tot = cnt[0] * cnt[1] * (D == 3 ? cnt[2] : 1);
+  for (int t = 0; t < tot; ++t) {
+    int rem = t;
+    long long off = 0;
+    double wgt = 1;
+    for (int a = D - 1; a >= 0; --a) { idx[a] = rem % cnt[a]; rem /= cnt[a]; }
+    for (int a = 0; a < D; ++a) { off += (long long)fi[a][idx[a]] * F.str[a]; wgt *= fw[a][idx[a]]; }
+    acc += wgt * (double)rf[F.voff + off];
+  }
+  rc[C.voff + jc] = (TV)(acc / (double)(1 << C.ncoarsened));
+}
+
+// Prolongation and correction x_f += P e_c over fine points.
+template <int D, typename TV>
+__global__ void __launch_bounds__(kBlock) k_prolong_add(const Work* __restrict__ work, const LInst* __restrict__ lf,
+                                                        const LInst* __restrict__ lc, const TV* __restrict__ ec,
+                                                        TV* __restrict__ xf) {
+  const Work wk = work[blockIdx.x];
+  const LInst& F = lf[wk.inst];
+  const LInst& C = lc[wk.inst];
+  const int jf = wk.start + threadIdx.x;
+  if (jf >= F.N) return;
+  int fc[kMaxD];
+  coords<D>(F, jf, fc);
+  int ci2[kMaxD][2];
+  double cw[kMaxD][2];
+  int cnt[kMaxD];
+  for (int a = 0; a < D; ++a) {
+    if (C.n[a] == F.n[a]) { cnt[a] = 1; ci2[a][0] = fc[a]; cw[a][0] = 1; continue; }
+    const int i = fc[a], X = i >> 1, ncn = C.n[a];
+    if ((i & 1) == 0) { cnt[a] = 1; ci2[a][0] = X; cw[a][0] = 1; }
+    else if (F.per[a]) { cnt[a] = 2; ci2[a][0] = X; cw[a][0] = 0.5; ci2[a][1] = (X + 1) % ncn; cw[a][1] = 0.5; }
+    else if (X + 1 < ncn) { cnt[a] = 2; ci2[a][0] = X; cw[a][0] = 0.5; ci2[a][1] = X + 1; cw[a][1] = 0.5; }
+    else { cnt[a] = 1; ci2[a][0] = X; cw[a][0] = 1; }
+  }
+  double acc = 0;
+  const int tot = cnt[0] * cnt[1] * (D == 3 ? cnt[2] : 1);
+  for (int t = 0; t < tot; ++t) {
+    int rem = t, idx[kMaxD];
+    for (int a = D - 1; a >= 0; --a) { idx[a] = rem % cnt[a]; rem /= cnt[a]; }
+    long long off = 0;
+    double wgt = 1;
+    for (int a = 0; a < D; ++a) { off += (long long)ci2[a][idx[a]] * C.str[a]; wgt *= cw[a][idx[a]]; }
+    acc += wgt * (double)ec[C.voff + off];
+  }
+  const long long g = F.voff + jf;
+  xf[g] = (TV)((double)xf[g] + acc);
+}
+
+// Coefficient coarsening: normalised full weighting along halved axes.
+template <int D, typename TC>
+__global__ void __launch_bounds__(kBlock) k_coarsen_coef(const Work* __restrict__ work, const LInst* __restrict__ lf,
+                                                         const LInst* __restrict__ lc, int K,
+                                                         const TC* __restrict__ cf, TC* __restrict__ cc) {
+  const Work wk = work[blockIdx.x];
+  const LInst& C = lc[wk.inst];
+  const LInst& F = lf[wk.inst];
+  const int jc = wk.start + threadIdx.x;
+  if (jc >= C.N) return;
+  int cq[kMaxD];
+  coords<D>(C, jc, cq);
+  int fi[kMaxD][3];
+  double fw[kMaxD][3];
+  int cnt[kMaxD];
+  for (int a = 0; a < D; ++a) {
+    if (C.n[a] == F.n[a]) { cnt[a] = 1; fi[a][0] = cq[a]; fw[a][0] = 1; continue; }
+    const int nf = F.n[a], X = cq[a];
+    int m = 0;
+    double tw = 0;
+    fi[a][m] = 2 * X; fw[a][m++] = 0.5;
+    if (F.per[a] || 2 * X - 1 >= 0) { fi[a][m] = (2 * X - 1 + nf) % nf; fw[a][m++] = 0.25; }
+    if (F.per[a] || 2 * X + 1 < nf) { fi[a][m] = (2 * X + 1) % nf; fw[a][m++] = 0.25; }
+    for (int q = 0; q < m; ++q) tw += fw[a][q];
+    for (int q = 0; q < m; ++q) fw[a][q] /= tw;
+    cnt[a] = m;
+  }
+  const int tot = cnt[0] * cnt[1] * (D == 3 ? cnt[2] : 1);
+  for (int k = 0; k < K; ++k) {
+    double acc = 0;
+    for (int t = 0; t < tot; ++t) {
+      int rem = t, idx[kMaxD];
+      for (int a = D - 1; a >= 0; --a) { idx[a] = rem % cnt[a]; rem /= cnt[a]; }
+      long long off = 0;
+      double wgt = 1;
+      for (int a = 0; a < D; ++a) { off += (long long)fi[a][idx[a]] * F.str[a]; wgt *= fw[a][idx[a]]; }
+      acc += wgt * (double)cf[F.coff + (long long)k * F.N + off];
+    }
+    cc[C.coff + (long long)k * C.N + jc] = (TC)acc;
+  }
+}
+
+// Unit columns for probing the coarsest operator: probe instance q holds the
+// unit vector of its own column, U[voff(q) + col(q)] = 1 (U zero-filled).
+__global__ void __launch_bounds__(kBlock) k_set_unit(const LInst* __restrict__ probe, const int* __restrict__ col,
+                                                     int nprobe, double* __restrict__ U) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < nprobe) U[probe[q].voff + col[q]] = 1.0;
+}
+
+// In-place Gauss-Jordan inverse of one SPD matrix per block (FP64, no
+// pivoting: the coarsest operator is symmetric positive definite).
+__global__ void __launch_bounds__(1024) k_gauss_jordan(double* __restrict__ A, const long long* __restrict__ off,
+                                                       const int* __restrict__ nn, int* __restrict__ fail) {
+  double* M = A + off[blockIdx.x];
+  const int n = nn[blockIdx.x];
+  __shared__ double prow[2048];
+  __shared__ double pcol[2048];
+  __shared__ double piv;
+  for (int k = 0; k < n; ++k) {
+    if (threadIdx.x == 0) {
+      piv = M[(long long)k * n + k];
+      if (!(piv > 0)) fail[blockIdx.x] = 1;
+    }
+    __syncthreads();
+    const double ip = 1.0 / piv;
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+      prow[c] = M[(long long)k * n + c] * ip;
+      pcol[c] = M[(long long)c * n + k];
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < n; c += blockDim.x) prow[c] = (c == k) ? ip : prow[c];
+    __syncthreads();
+    for (long long e = threadIdx.x; e < (long long)n * n; e += blockDim.x) {
+      const int r = (int)(e / n), c = (int)(e - (long long)r * n);
+      if (r == k) M[e] = prow[c];
+      else {
+        const double f = pcol[r];
+        M[e] = (c == k ? 0.0 : M[e]) - f * prow[c];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename TV>
+__global__ void __launch_bounds__(kBlock) k_convert_dense(const double* __restrict__ src, TV* __restrict__ dst, long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (TV)src[i];
+}
+
+// e = Sinv r for coarsest instances: one thread per row; Sinv symmetric, so
+// row r is read as column r (coalesced across threads).
+template <typename TV>
+__global__ void __launch_bounds__(kBlock) k_dense_apply(const Work* __restrict__ work, const LInst* __restrict__ li,
+                                                        const TV* __restrict__ Sinv, const TV* __restrict__ r,
+                                                        TV* __restrict__ e) {
+  const Work wk = work[blockIdx.x];
+  const LInst& L = li[wk.inst];
+  const int row = wk.start + threadIdx.x;
+  const int n = L.N;
+  const TV* M = Sinv + L.doff;
+  const TV* rr = r + L.voff;
+  __shared__ TV rs[kBlock];
+  double acc = 0;
+  for (int c0 = 0; c0 < n; c0 += kBlock) {
+    __syncthreads();
+    if (c0 + (int)threadIdx.x < n) rs[threadIdx.x] = rr[c0 + threadIdx.x];
+    __syncthreads();
+    const int cmax = (n - c0) < kBlock ? (n - c0) : kBlock;
+    if (row < n)
+      for (int cc = 0; cc < cmax; ++cc) acc += (double)M[(long long)(c0 + cc) * n + row] * (double)rs[cc];
+  }
+  if (row < n) e[L.voff + row] = (TV)acc;
+}
+
+// ---------------------------------------------------------------- Krylov
+template <typename TA, typename TV>
+__global__ void __launch_bounds__(kBlock) k_dot(const Work* __restrict__ work, const LInst* __restrict__ li,
+                                                const TV* __restrict__ a, const TV* __restrict__ b,
+                                                double* __restrict__ partial) {
+  const Work wk = work[blockIdx.x];
+  const LInst& L = li[wk.inst];
+  const int j = wk.start + threadIdx.x;
+  double v = 0;
+  if (j < L.N) v = (double)a[L.voff + j] * (double)b[L.voff + j];
+  v = block_sum(v);
+  if (threadIdx.x == 0) partial[blockIdx.x] = v;
+}
+
+// Per-instance fixed-order sum of block partials: out[b] = sum partial[bs[b]..bs[b+1]).
+__global__ void k_finish_sum(const double* __restrict__ partial, const int* __restrict__ bstart, int B,
+                             double* __restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  double s = 0;
+  for (int i = bstart[b]; i < bstart[b + 1]; ++i) s += partial[i];
+  out[b] = s;
+}
+
+// Scalar updates of PCG, one thread per instance.
+//   op 0: beta = active ? (first ? 0 : rz_new/rz) : 0; rz = rz_new
+//   op 1: alpha = active ? rz/pq : 0
+//   op 2: convergence test of rnorm2 against tol2*r0norm2; counts iterations
+__global__ void k_pcg_scalars(int op, int B, int first, double tol2, double* __restrict__ rz_new,
+                              double* __restrict__ rz, double* __restrict__ beta, double* __restrict__ pq,
+                              double* __restrict__ alpha, double* __restrict__ rn2, double* __restrict__ r0n2,
+                              int* __restrict__ active, int* __restrict__ iters) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  if (op == 0) {
+    const double v = rz_new[b];
+    beta[b] = (active[b] && !first && rz[b] != 0.0) ? v / rz[b] : 0.0;
+    rz[b] = v;
+  } else if (op == 1) {
+    const double d = pq[b];
+    alpha[b] = (active[b] && d > 0.0 && isfinite(d)) ? rz[b] / d : 0.0;
+  } else {
+    if (active[b]) {
+      iters[b] += 1;
+      const double r = rn2[b];
+      if (!(r > tol2 * r0n2[b])) active[b] = 0;   // converged or non-finite
+    }
+  }
+}
+
+// p = z + beta p
+template <typename TV>
+__global__ void __launch_bounds__(kBlock) k_update_p(const Work* __restrict__ work, const LInst* __restrict__ li,
+                                                     const double* __restrict__ beta, const TV* __restrict__ z,
+                                                     TV* __restrict__ p) {
+  const Work wk = work[blockIdx.x];
+  const LInst& L = li[wk.inst];
+  const int j = wk.start + threadIdx.x;
+  if (j >= L.N) return;
+  const long long g = L.voff + j;
+  const double bt = beta[wk.inst];
+  p[g] = (TV)((double)z[g] + bt * (double)p[g]);
+}
+
+// x += alpha p; r -= alpha q; partial ||r||^2
+template <typename TV>
+__global__ void __launch_bounds__(kBlock) k_update_xr(const Work* __restrict__ work, const LInst* __restrict__ li,
+                                                      const double* __restrict__ alpha, const TV* __restrict__ p,
+                                                      const TV* __restrict__ q, TV* __restrict__ x,
+                                                      TV* __restrict__ r, double* __restrict__ partial) {
+  const Work wk = work[blockIdx.x];
+  const LInst& L = li[wk.inst];
+  const int j = wk.start + threadIdx.x;
+  double v = 0;
+  if (j < L.N) {
+    const long long g = L.voff + j;
+    const double al = alpha[wk.inst];
+    x[g] = (TV)((double)x[g] + al * (double)p[g]);
+    const TV rr = (TV)((double)r[g] - al * (double)q[g]);
+    r[g] = rr;
+    v = (double)rr * (double)rr;
+  }
+  v = block_sum(v);
+  if (threadIdx.x == 0) partial[blockIdx.x] = v;
+}
+
+// Elementwise helpers for the refinement loop.
+template <typename TS, typename TD>
+__global__ void __launch_bounds__(kBlock) k_copy_scale(const Work* __restrict__ work, const LInst* __restrict__ li,
+                                                       const TS* __restrict__ s, TD* __restrict__ d,
+                                                       const double* __restrict__ scale, int add) {
+  const Work wk = work[blockIdx.x];
+  const LInst& L = li[wk.inst];
+  const int j = wk.start + threadIdx.x;
+  if (j >= L.N) return;
+  const long long g = L.voff + j;
+  const double sc = scale ? scale[wk.inst] : 1.0;
+  const double v = sc * (double)s[g];
+  d[g] = add ? (TD)((double)d[g] + v) : (TD)v;
+}
+
+template <typename TV>
+__global__ void __launch_bounds__(kBlock) k_fill(const Work* __restrict__ work, const LInst* __restrict__ li,
+                                                 TV* __restrict__ d, double v) {
+  const Work wk = work[blockIdx.x];
+  const LInst& L = li[wk.inst];
+  const int j = wk.start + threadIdx.x;
+  if (j >= L.N) return;
+  d[L.voff + j] = (TV)v;
+}
+
+// ||A^T d||^2 partials: (A^T d)_u = c_phi f + [B] omega, (A^T d)_m = c_m f.
+template <int D, typename TC>
+__global__ void __launch_bounds__(kBlock) k_atd_norm(const Work* __restrict__ work, const LInst* __restrict__ li,
+                                                     CIdx ci, const TC* __restrict__ c, const TC* __restrict__ f,
+                                                     const TC* __restrict__ w, double* __restrict__ partial) {
+  const Work wk = work[blockIdx.x];
+  const LInst& L = li[wk.inst];
+  const int j = wk.start + threadIdx.x;
+  double v = 0;
+  if (j < L.N) {
+    int ic[kMaxD];
+    coords<D>(L, j, ic);
+    bool onB = false;
+    for (int a = 0; a < D; ++a) onB |= (L.dlo[a] && ic[a] == 0) || (L.dhi[a] && ic[a] == L.n[a] - 1);
+    const double fj = (double)f[L.voff + j];
+    double tu = coef(c, L, ci.k[0], j) * fj + (onB ? (double)w[L.voff + j] : 0.0);
+    v = tu * tu;
+    for (int m = 1; m < 1 + 2 * D; ++m) {
+      const double t = coef(c, L, ci.k[m], j) * fj;
+      v += t * t;
+    }
+  }
+  v = block_sum(v);
+  if (threadIdx.x == 0) partial[blockIdx.x] = v;
+}
+
+// Local optimum of the derivative unknowns at p given u (and sigma*d); writes
+// the scaled values xs[2a] = p_a, xs[2a+1] = q_a.  rhs_w (optional) adds a
+// right-hand side in the scaled derivative unknowns (backward pass).
+template <int D>
+__device__ void local_derivs(const LInst& L, const CIdx& ci, const double* u, const double* cpl,
+                             double fterm, const double* rw, long long p, const int* ic, double* xs,
+                             double* rhoE_out, double ui) {
+  // cpl: coefficient values at p per variable (0 if absent)
+  double rhoE = cpl[0] * ui - fterm;
+  double b1[kMaxD], b2[kMaxD], i11[kMaxD], i12[kMaxD], i22[kMaxD], ca[kMaxD], caa[kMaxD];
+  double kap = 1, num = rhoE;
+  for (int a = 0; a < D; ++a) {
+    AxisRows<double, double> R = axis_rows<double, double>(L, a, u, p, ic[a], ui);
+    ginv<double>(L, a, R.tp, R.tm, i11[a], i12[a], i22[a]);
+    const double wT = L.wT[a];
+    // A_w^T rho with rho = rows of u; the backward pass subtracts a rhs.
+    b1[a] = wT * (R.rTp - R.rTm) + L.wC1[a] * R.rC1;
+    b2[a] = wT * (R.rTp + R.rTm) * 0.5 + L.wC2[a] * R.rC2;
+    if (rw) { b1[a] -= rw[2 * a]; b2[a] -= rw[2 * a + 1]; }
+    ca[a] = cpl[1 + 2 * a] / L.s[a];
+    caa[a] = cpl[2 + 2 * a] / (L.s[a] * L.s[a]);
+  }
+  // M x = -(c^ rhoE + b)  with M = G + c^ c^^T  (Sherman-Morrison)
+  double g1[kMaxD], g2[kMaxD], h1[kMaxD], h2[kMaxD];
+  for (int a = 0; a < D; ++a) {
+    g1[a] = i11[a] * b1[a] + i12[a] * b2[a];
+    g2[a] = i12[a] * b1[a] + i22[a] * b2[a];
+    h1[a] = i11[a] * ca[a] + i12[a] * caa[a];
+    h2[a] = i12[a] * ca[a] + i22[a] * caa[a];
+    kap += ca[a] * h1[a] + caa[a] * h2[a];
+    num -= ca[a] * g1[a] + caa[a] * g2[a];
+  }
+  const double gam = num / kap;
+  for (int a = 0; a < D; ++a) {
+    xs[2 * a] = -(g1[a] + h1[a] * gam);
+    xs[2 * a + 1] = -(g2[a] + h2[a] * gam);
+  }
+  if (rhoE_out) *rhoE_out = gam;
+}
+
+// z_out (all V planes, physical units) from u (FP64).
+template <int D, typename TC, typename TO>
+__global__ void __launch_bounds__(kBlock) k_output(const Work* __restrict__ work, const LInst* __restrict__ li,
+                                                   CIdx ci, const double* __restrict__ u, const TC* __restrict__ c,
+                                                   const TC* __restrict__ f, TO* __restrict__ z,
+                                                   const long long* __restrict__ zoff) {
+  const Work wk = work[blockIdx.x];
+  const LInst& L = li[wk.inst];
+  const int j = wk.start + threadIdx.x;
+  if (j >= L.N) return;
+  int ic[kMaxD];
+  coords<D>(L, j, ic);
+  double cpl[1 + 2 * kMaxD];
+  for (int v = 0; v < 1 + 2 * D; ++v) cpl[v] = coef(c, L, ci.k[v], j);
+  double xs[2 * kMaxD];
+  const double ui = u[L.voff + j];
+  local_derivs<D>(L, ci, u + L.voff, cpl, (double)f[L.voff + j], nullptr, j, ic, xs, nullptr, ui);
+  TO* Z = z + zoff[wk.inst];
+  Z[j] = (TO)ui;
+  for (int a = 0; a < D; ++a) {
+    Z[(long long)(1 + 2 * a) * L.N + j] = (TO)(xs[2 * a] / L.s[a]);
+    Z[(long long)(2 + 2 * a) * L.N + j] = (TO)(xs[2 * a + 1] / (L.s[a] * L.s[a]));
+  }
+}
+
+// Backward pass, step 1: v_i = M_i^-1 g~_w,i  (scaled derivative rhs) stored
+// as 2D planes; g~_p = g_{u_a}/s_a, g~_q = g_{u_aa}/s_a^2.
+template <int D, typename TC, typename TG>
+__global__ void __launch_bounds__(kBlock) k_adj_local(const Work* __restrict__ work, const LInst* __restrict__ li,
+                                                      CIdx ci, const TC* __restrict__ c, const TG* __restrict__ gz,
+                                                      const long long* __restrict__ zoff, double* __restrict__ vloc) {
+  const Work wk = work[blockIdx.x];
+  const LInst& L = li[wk.inst];
+  const int j = wk.start + threadIdx.x;
+  if (j >= L.N) return;
+  int ic[kMaxD];
+  coords<D>(L, j, ic);
+  const TG* G = gz + zoff[wk.inst];
+  double r1[kMaxD], r2[kMaxD], i11[kMaxD], i12[kMaxD], i22[kMaxD], ca[kMaxD], caa[kMaxD];
+  double kap = 1, num = 0;
+  double g1[kMaxD], g2[kMaxD], h1[kMaxD], h2[kMaxD];
+  for (int a = 0; a < D; ++a) {
+    int tp, tm, wp;
+    axis_class(ic[a], L.n[a], L.per[a], tp, tm, wp);
+    ginv<double>(L, a, tp, tm, i11[a], i12[a], i22[a]);
+    r1[a] = (double)G[(long long)(1 + 2 * a) * L.N + j] / L.s[a];
+    r2[a] = (double)G[(long long)(2 + 2 * a) * L.N + j] / (L.s[a] * L.s[a]);
+    chat<double, TC>(L, ci, c, a, j, ca[a], caa[a]);
+    g1[a] = i11[a] * r1[a] + i12[a] * r2[a];
+    g2[a] = i12[a] * r1[a] + i22[a] * r2[a];
+    h1[a] = i11[a] * ca[a] + i12[a] * caa[a];
+    h2[a] = i12[a] * ca[a] + i22[a] * caa[a];
+    kap += ca[a] * h1[a] + caa[a] * h2[a];
+    num += ca[a] * g1[a] + caa[a] * g2[a];
+  }
+  const double t = num / kap;
+  double* V = vloc + (long long)2 * D * L.voff;
+  for (int a = 0; a < D; ++a) {
+    V[(long long)(2 * a) * L.N + j] = g1[a] - h1[a] * t;
+    V[(long long)(2 * a + 1) * L.N + j] = g2[a] - h2[a] * t;
+  }
+}
+
+// Backward pass, step 2: g^_j = g_u,j - (A_u^T A_w v)_j.
+template <int D, typename TC, typename TG>
+__global__ void __launch_bounds__(kBlock) k_adj_rhs(const Work* __restrict__ work, const LInst* __restrict__ li,
+                                                    CIdx ci, const TC* __restrict__ c, const TG* __restrict__ gz,
+                                                    const long long* __restrict__ zoff,
+                                                    const double* __restrict__ vloc, double* __restrict__ ghat) {
+  const Work wk = work[blockIdx.x];
+  const LInst& L = li[wk.inst];
+  const int j = wk.start + threadIdx.x;
+  if (j >= L.N) return;
+  int ic[kMaxD];
+  coords<D>(L, j, ic);
+  const double* V = vloc + (long long)2 * D * L.voff;
+  double zE = 0;
+  for (int a = 0; a < D; ++a) {
+    double ca, caa;
+    chat<double, TC>(L, ci, c, a, j, ca, caa);
+    zE += ca * V[(long long)(2 * a) * L.N + j] + caa * V[(long long)(2 * a + 1) * L.N + j];
+  }
+  double y = coef(c, L, ci.k[0], j) * zE;
+  for (int a = 0; a < D; ++a) {
+    const int n = L.n[a], st = L.str[a], per = L.per[a], ia = ic[a];
+    const double wT = L.wT[a];
+    const int R = per ? 2 : 4;
+    for (int o = -R; o <= R; ++o) {
+      const int ii = ia + o;
+      if (!per && (ii < 0 || ii >= n)) continue;
+      const int iw = per ? ((ii % n) + n) % n : ii;
+      int tp, tm, wp;
+      axis_class(iw, n, per, tp, tm, wp);
+      const int k = wp - o;
+      const bool inC = (k >= 0 && k <= 4);
+      const bool inT = (o >= -1 && o <= 1);
+      if (!inC && !inT) continue;
+      const long long pi = nbr(j, ia, o, n, st, per);
+      const double vp = V[(long long)(2 * a) * L.N + pi], vq = V[(long long)(2 * a + 1) * L.N + pi];
+      const double zTp = tp ? wT * (vp + 0.5 * vq) : 0, zTm = tm ? wT * (-vp + 0.5 * vq) : 0;
+      const double zC1 = L.wC1[a] * vp, zC2 = L.wC2[a] * vq;
+      if (inC) y -= L.wC1[a] * c_W1[wp][k] * zC1 + L.wC2[a] * c_W2[wp][k] * zC2;
+      if (o == 0) y += wT * (zTp + zTm);
+      else if (o == -1) y -= wT * zTp;
+      else if (o == 1) y -= wT * zTm;
+    }
+  }
+  const TG* G = gz + zoff[wk.inst];
+  ghat[L.voff + j] = (double)G[j] - y;
+}
+
+// Backward pass, step 3: d_z from d_u, the dual variables and the gradients.
+template <int D, typename TC, typename TG>
+__global__ void __launch_bounds__(kBlock) k_adj_grad(const Work* __restrict__ work, const LInst* __restrict__ li,
+                                                     CIdx ci, const TC* __restrict__ c, const TC* __restrict__ f,
+                                                     const double* __restrict__ ustar, const double* __restrict__ du,
+                                                     const TG* __restrict__ gz, const long long* __restrict__ zoff,
+                                                     TG* __restrict__ gc, TG* __restrict__ gf, TG* __restrict__ gw) {
+  const Work wk = work[blockIdx.x];
+  const LInst& L = li[wk.inst];
+  const int j = wk.start + threadIdx.x;
+  if (j >= L.N) return;
+  int ic[kMaxD];
+  coords<D>(L, j, ic);
+  double cpl[1 + 2 * kMaxD];
+  for (int v = 0; v < 1 + 2 * D; ++v) cpl[v] = coef(c, L, ci.k[v], j);
+  const double fj = (double)f[L.voff + j];
+  // z* at j (physical units)
+  double xs[2 * kMaxD], zs[1 + 2 * kMaxD];
+  const double us = ustar[L.voff + j];
+  local_derivs<D>(L, ci, ustar + L.voff, cpl, fj, nullptr, j, ic, xs, nullptr, us);
+  zs[0] = us;
+  for (int a = 0; a < D; ++a) { zs[1 + 2 * a] = xs[2 * a] / L.s[a]; zs[2 + 2 * a] = xs[2 * a + 1] / (L.s[a] * L.s[a]); }
+  // d_z at j: derivative unknowns minimise the local rows with rhs g~_w
+  const TG* G = gz + zoff[wk.inst];
+  double rw[2 * kMaxD];
+  for (int a = 0; a < D; ++a) {
+    rw[2 * a] = (double)G[(long long)(1 + 2 * a) * L.N + j] / L.s[a];
+    rw[2 * a + 1] = (double)G[(long long)(2 + 2 * a) * L.N + j] / (L.s[a] * L.s[a]);
+  }
+  double dx[2 * kMaxD], dzv[1 + 2 * kMaxD];
+  const double duj = du[L.voff + j];
+  local_derivs<D>(L, ci, du + L.voff, cpl, 0.0, rw, j, ic, dx, nullptr, duj);
+  dzv[0] = duj;
+  for (int a = 0; a < D; ++a) { dzv[1 + 2 * a] = dx[2 * a] / L.s[a]; dzv[2 + 2 * a] = dx[2 * a + 1] / (L.s[a] * L.s[a]); }
+  double Az = 0, Adz = 0;
+  for (int v = 0; v < 1 + 2 * D; ++v) { Az += cpl[v] * zs[v]; Adz += cpl[v] * dzv[v]; }
+  const double lamE = fj - Az;       // lambda* on the equation row
+  const double dlamE = -Adz;         // d_lambda = -A d_z on the equation row
+  if (gc) {
+    TG* GC = gc + L.coff;
+    for (int v = 0; v < 1 + 2 * D; ++v) {
+      const int k = ci.k[v];
+      if (k < 0) continue;
+      GC[(long long)k * L.N + j] = (TG)(dlamE * zs[v] + lamE * dzv[v]);
+    }
+  }
+  if (gf) gf[L.voff + j] = (TG)(-dlamE);
+  if (gw) {
+    bool onB = false;
+    for (int a = 0; a < D; ++a) onB |= (L.dlo[a] && ic[a] == 0) || (L.dhi[a] && ic[a] == L.n[a] - 1);
+    gw[L.voff + j] = (TG)(onB ? duj : 0.0);
+  }
+}
+
+// Non-finite scan of an input array: flag[0] |= any element is NaN/Inf.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_nonfinite(const T* __restrict__ a, long long n, int* __restrict__ flag) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !isfinite((double)a[i])) flag[0] = 1;
+}
+
+// ---------------------------------------------------------------- launchers
+#define GRID(nb) dim3((unsigned)(nb)), dim3(kBlock), 0, st
+
+template <typename TA, typename TV, typename TC>
+void launch_gamma(int D, hipStream_t st, const Work* w, int nb, const LInst* li, CIdx ci, const TV* u,
+                  const TC* c, const TC* f, int sigma, TV* gam) {
+  if (nb <= 0) return;
+  if (D == 2) hipLaunchKernelGGL((k_gamma<2, TA, TV, TC>), GRID(nb), w, li, ci, u, c, f, sigma, gam);
+  else hipLaunchKernelGGL((k_gamma<3, TA, TV, TC>), GRID(nb), w, li, ci, u, c, f, sigma, gam);
+}
+
+template <typename TA, typename TV, typename TC>
+void launch_gather(int D, hipStream_t st, const Work* w, int nb, const LInst* li, CIdx ci, const TV* u,
+                   const TV* gam, const TC* c, const TC* bw, int sigma, int mode, TV* out, const TV* bvec,
+                   TV* x, TV* r, TV* d, const TV* dinv, int cheb_step, double* partial) {
+  if (nb <= 0) return;
+  if (D == 2)
+    hipLaunchKernelGGL((k_gather<2, TA, TV, TC>), GRID(nb), w, li, ci, u, gam, c, bw, sigma, mode, out, bvec, x, r,
+                       d, dinv, cheb_step, partial);
+  else
+    hipLaunchKernelGGL((k_gather<3, TA, TV, TC>), GRID(nb), w, li, ci, u, gam, c, bw, sigma, mode, out, bvec, x, r,
+                       d, dinv, cheb_step, partial);
+}
+
+template <typename TV, typename TC>
+void launch_diag(int D, hipStream_t st, const Work* w, int nb, const LInst* li, CIdx ci, const TC* c, TV* dinv) {
+  if (nb <= 0) return;
+  if (D == 2) hipLaunchKernelGGL((k_diag<2, TV, TC>), GRID(nb), w, li, ci, c, dinv);
+  else hipLaunchKernelGGL((k_diag<3, TV, TC>), GRID(nb), w, li, ci, c, dinv);
+}
+
+template <typename TV>
+void launch_cheb_init(hipStream_t st, const Work* w, int nb, const LInst* li, const TV* b, const TV* dinv, TV* x,
+                      TV* r, TV* d) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL((k_cheb_init<TV>), GRID(nb), w, li, b, dinv, x, r, d);
+}
+
+template <typename TV>
+void launch_restrict(int D, hipStream_t st, const Work* w, int nb, const LInst* lf, const LInst* lc, const TV* rf,
+                     TV* rc) {
+  if (nb <= 0) return;
+  if (D == 2) hipLaunchKernelGGL((k_restrict<2, TV>), GRID(nb), w, lf, lc, rf, rc);
+  else hipLaunchKernelGGL((k_restrict<3, TV>), GRID(nb), w, lf, lc, rf, rc);
+}
+
+template <typename TV>
+void launch_prolong_add(int D, hipStream_t st, const Work* w, int nb, const LInst* lf, const LInst* lc,
+                        const TV* ec, TV* xf) {
+  if (nb <= 0) return;
+  if (D == 2) hipLaunchKernelGGL((k_prolong_add<2, TV>), GRID(nb), w, lf, lc, ec, xf);
+  else hipLaunchKernelGGL((k_prolong_add<3, TV>), GRID(nb), w, lf, lc, ec, xf);
+}
+
+template <typename TC>
+void launch_coarsen_coef(int D, hipStream_t st, const Work* w, int nb, const LInst* lf, const LInst* lc, int K,
+                         const TC* cf, TC* cc) {
+  if (nb <= 0) return;
+  if (D == 2) hipLaunchKernelGGL((k_coarsen_coef<2, TC>), GRID(nb), w, lf, lc, K, cf, cc);
+  else hipLaunchKernelGGL((k_coarsen_coef<3, TC>), GRID(nb), w, lf, lc, K, cf, cc);
+}
+
+void launch_set_unit(hipStream_t st, const LInst* probe, const int* col, int nprobe, double* U) {
+  if (nprobe <= 0) return;
+  hipLaunchKernelGGL(k_set_unit, dim3((nprobe + 255) / 256), dim3(256), 0, st, probe, col, nprobe, U);
+}
+
+void launch_gauss_jordan(hipStream_t st, int nmat, double* A, const long long* off, const int* n, int* fail) {
+  if (nmat <= 0) return;
+  hipLaunchKernelGGL(k_gauss_jordan, dim3(nmat), dim3(1024), 0, st, A, off, n, fail);
+}
+
+template <typename TV>
+void launch_convert_dense(hipStream_t st, const double* src, TV* dst, long long n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((k_convert_dense<TV>), dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, src,
+                     dst, n);
+}
+
+template <typename TV>
+void launch_dense_apply(hipStream_t st, const Work* w, int nb, const LInst* li, const TV* Sinv, const TV* r, TV* e) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL((k_dense_apply<TV>), GRID(nb), w, li, Sinv, r, e);
+}
+
+template <typename TA, typename TV>
+void launch_dot(hipStream_t st, const Work* w, int nb, const LInst* li, const TV* a, const TV* b, double* partial) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL((k_dot<TA, TV>), GRID(nb), w, li, a, b, partial);
+}
+
+void launch_finish_sum(hipStream_t st, const double* partial, const int* bstart, int B, double* out) {
+  hipLaunchKernelGGL(k_finish_sum, dim3((B + 255) / 256), dim3(256), 0, st, partial, bstart, B, out);
+}
+
+void launch_pcg_scalars(hipStream_t st, int op, int B, int first, double tol2, double* rz_new, double* rz,
+                        double* beta, double* pq, double* alpha, double* rn2, double* r0n2, int* active,
+                        int* iters) {
+  hipLaunchKernelGGL(k_pcg_scalars, dim3((B + 255) / 256), dim3(256), 0, st, op, B, first, tol2, rz_new, rz, beta,
+                     pq, alpha, rn2, r0n2, active, iters);
+}
+
+template <typename TV>
+void launch_update_p(hipStream_t st, const Work* w, int nb, const LInst* li, const double* beta, const TV* z,
+                     TV* p) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL((k_update_p<TV>), GRID(nb), w, li, beta, z, p);
+}
+
+template <typename TV>
+void launch_update_xr(hipStream_t st, const Work* w, int nb, const LInst* li, const double* alpha, const TV* p,
+                      const TV* q, TV* x, TV* r, double* partial) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL((k_update_xr<TV>), GRID(nb), w, li, alpha, p, q, x, r, partial);
+}
+
+template <typename TS, typename TD>
+void launch_copy_scale(hipStream_t st, const Work* w, int nb, const LInst* li, const TS* s, TD* d,
+                       const double* scale, int add) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL((k_copy_scale<TS, TD>), GRID(nb), w, li, s, d, scale, add);
+}
+
+template <typename TV>
+void launch_fill(hipStream_t st, const Work* w, int nb, const LInst* li, TV* d, double v) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL((k_fill<TV>), GRID(nb), w, li, d, v);
+}
+
+template <typename TC>
+void launch_atd_norm(int D, hipStream_t st, const Work* w, int nb, const LInst* li, CIdx ci, const TC* c,
+                     const TC* f, const TC* bw, double* partial) {
+  if (D == 2) hipLaunchKernelGGL((k_atd_norm<2, TC>), GRID(nb), w, li, ci, c, f, bw, partial);
+  else hipLaunchKernelGGL((k_atd_norm<3, TC>), GRID(nb), w, li, ci, c, f, bw, partial);
+}
+
+template <typename TC, typename TO>
+void launch_output(int D, hipStream_t st, const Work* w, int nb, const LInst* li, CIdx ci, const double* u,
+                   const TC* c, const TC* f, TO* z, const long long* zoff) {
+  if (D == 2) hipLaunchKernelGGL((k_output<2, TC, TO>), GRID(nb), w, li, ci, u, c, f, z, zoff);
+  else hipLaunchKernelGGL((k_output<3, TC, TO>), GRID(nb), w, li, ci, u, c, f, z, zoff);
+}
+
+template <typename TC, typename TG>
+void launch_adj_local(int D, hipStream_t st, const Work* w, int nb, const LInst* li, CIdx ci, const TC* c,
+                      const TG* gz, const long long* zoff, double* vloc) {
+  if (D == 2) hipLaunchKernelGGL((k_adj_local<2, TC, TG>), GRID(nb), w, li, ci, c, gz, zoff, vloc);
+  else hipLaunchKernelGGL((k_adj_local<3, TC, TG>), GRID(nb), w, li, ci, c, gz, zoff, vloc);
+}
+
+template <typename TC, typename TG>
+void launch_adj_rhs(int D, hipStream_t st, const Work* w, int nb, const LInst* li, CIdx ci, const TC* c,
+                    const TG* gz, const long long* zoff, const double* vloc, double* ghat) {
+  if (D == 2) hipLaunchKernelGGL((k_adj_rhs<2, TC, TG>), GRID(nb), w, li, ci, c, gz, zoff, vloc, ghat);
+  else hipLaunchKernelGGL((k_adj_rhs<3, TC, TG>), GRID(nb), w, li, ci, c, gz, zoff, vloc, ghat);
+}
+
+template <typename TC, typename TG>
+void launch_adj_grad(int D, hipStream_t st, const Work* w, int nb, const LInst* li, CIdx ci, const TC* c,
+                     const TC* f, const double* ustar, const double* du, const TG* gz, const long long* zoff,
+                     TG* gc, TG* gf, TG* gw) {
+  if (D == 2)
+    hipLaunchKernelGGL((k_adj_grad<2, TC, TG>), GRID(nb), w, li, ci, c, f, ustar, du, gz, zoff, gc, gf, gw);
+  else
+    hipLaunchKernelGGL((k_adj_grad<3, TC, TG>), GRID(nb), w, li, ci, c, f, ustar, du, gz, zoff, gc, gf, gw);
+}
+
+template <typename T>
+void launch_nonfinite(hipStream_t st, const T* a, long long n, int* flag) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((k_nonfinite<T>), dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, a, n, flag);
+}
+
+// ---------------------------------------------------------------- instantiations
+#define INST_TV_TC(TA, TV, TC)                                                                                   \
+  template void launch_gamma<TA, TV, TC>(int, hipStream_t, const Work*, int, const LInst*, CIdx, const TV*,       \
+                                         const TC*, const TC*, int, TV*);                                         \
+  template void launch_gather<TA, TV, TC>(int, hipStream_t, const Work*, int, const LInst*, CIdx, const TV*,      \
+                                          const TV*, const TC*, const TC*, int, int, TV*, const TV*, TV*, TV*,    \
+                                          TV*, const TV*, int, double*);
+INST_TV_TC(float, float, float)
+INST_TV_TC(double, double, float)
+INST_TV_TC(double, double, double)
+
+#define INST_TV(TV)                                                                                              \
+  template void launch_cheb_init<TV>(hipStream_t, const Work*, int, const LInst*, const TV*, const TV*, TV*, TV*, \
+                                     TV*);                                                                        \
+  template void launch_restrict<TV>(int, hipStream_t, const Work*, int, const LInst*, const LInst*, const TV*,    \
+                                    TV*);                                                                         \
+  template void launch_prolong_add<TV>(int, hipStream_t, const Work*, int, const LInst*, const LInst*, const TV*, \
+                                       TV*);                                                                      \
+  template void launch_convert_dense<TV>(hipStream_t, const double*, TV*, long long);                             \
+  template void launch_dense_apply<TV>(hipStream_t, const Work*, int, const LInst*, const TV*, const TV*, TV*);   \
+  template void launch_dot<double, TV>(hipStream_t, const Work*, int, const LInst*, const TV*, const TV*,         \
+                                       double*);                                                                  \
+  template void launch_update_p<TV>(hipStream_t, const Work*, int, const LInst*, const double*, const TV*, TV*);  \
+  template void launch_update_xr<TV>(hipStream_t, const Work*, int, const LInst*, const double*, const TV*,       \
+                                     const TV*, TV*, TV*, double*);                                               \
+  template void launch_fill<TV>(hipStream_t, const Work*, int, const LInst*, TV*, double);
+INST_TV(float)
+INST_TV(double)
+
+template void launch_diag<float, float>(int, hipStream_t, const Work*, int, const LInst*, CIdx, const float*, float*);
+template void launch_diag<double, double>(int, hipStream_t, const Work*, int, const LInst*, CIdx, const double*,
+                                          double*);
+template void launch_diag<double, float>(int, hipStream_t, const Work*, int, const LInst*, CIdx, const float*,
+                                         double*);
+template void launch_coarsen_coef<float>(int, hipStream_t, const Work*, int, const LInst*, const LInst*, int,
+                                         const float*, float*);
+template void launch_coarsen_coef<double>(int, hipStream_t, const Work*, int, const LInst*, const LInst*, int,
+                                          const double*, double*);
+template void launch_copy_scale<double, float>(hipStream_t, const Work*, int, const LInst*, const double*, float*,
+                                               const double*, int);
+template void launch_copy_scale<float, double>(hipStream_t, const Work*, int, const LInst*, const float*, double*,
+                                               const double*, int);
+template void launch_copy_scale<double, double>(hipStream_t, const Work*, int, const LInst*, const double*,
+                                                double*, const double*, int);
+template void launch_atd_norm<float>(int, hipStream_t, const Work*, int, const LInst*, CIdx, const float*,
+                                     const float*, const float*, double*);
+template void launch_atd_norm<double>(int, hipStream_t, const Work*, int, const LInst*, CIdx, const double*,
+                                      const double*, const double*, double*);
+template void launch_output<float, float>(int, hipStream_t, const Work*, int, const LInst*, CIdx, const double*,
+                                          const float*, const float*, float*, const long long*);
+template void launch_output<double, double>(int, hipStream_t, const Work*, int, const LInst*, CIdx,
+                                            const double*, const double*, const double*, double*,
+                                            const long long*);
+template void launch_adj_local<float, float>(int, hipStream_t, const Work*, int, const LInst*, CIdx, const float*,
+                                             const float*, const long long*, double*);
+template void launch_adj_local<double, double>(int, hipStream_t, const Work*, int, const LInst*, CIdx,
+                                               const double*, const double*, const long long*, double*);
+template void launch_adj_rhs<float, float>(int, hipStream_t, const Work*, int, const LInst*, CIdx, const float*,
+                                           const float*, const long long*, const double*, double*);
+template void launch_adj_rhs<double, double>(int, hipStream_t, const Work*, int, const LInst*, CIdx, const double*,
+                                             const double*, const long long*, const double*, double*);
+template void launch_adj_grad<float, float>(int, hipStream_t, const Work*, int, const LInst*, CIdx, const float*,
+                                            const float*, const double*, const double*, const float*,
+                                            const long long*, float*, float*, float*);
+template void launch_adj_grad<double, double>(int, hipStream_t, const Work*, int, const LInst*, CIdx,
+                                              const double*, const double*, const double*, const double*,
+                                              const double*, const long long*, double*, double*, double*);
+template void launch_nonfinite<float>(hipStream_t, const float*, long long, int*);
+template void launch_nonfinite<double>(hipStream_t, const double*, long long, int*);
+
+// Power iteration helpers for the Chebyshev interval of D^-1 S.
+template <typename TV>
+__global__ void __launch_bounds__(kBlock) k_hash_fill(const Work* __restrict__ work, const LInst* __restrict__ li,
+                                                      TV* __restrict__ v, unsigned seed) {
+  const Work wk = work[blockIdx.x];
+  const LInst& L = li[wk.inst];
+  const int j = wk.start + threadIdx.x;
+  if (j >= L.N) return;
+  unsigned h = (unsigned)(L.voff + j) * 2654435761u ^ (seed * 2246822519u + 0x9e3779b9u);
+  h ^= h >> 15; h *= 2246822519u; h ^= h >> 13; h *= 3266489917u; h ^= h >> 16;
+  v[L.voff + j] = (TV)((double)(h & 0xffffff) / (double)0x800000 - 1.0);
+}
+
+template <typename TV>
+__global__ void __launch_bounds__(kBlock) k_mul_dinv(const Work* __restrict__ work, const LInst* __restrict__ li,
+                                                     const TV* __restrict__ dinv, const TV* __restrict__ y,
+                                                     TV* __restrict__ v, double* __restrict__ partial) {
+  // v = D^-1 y, partial = sum v^2 / dinv  (= v^T D v)
+  const Work wk = work[blockIdx.x];
+  const LInst& L = li[wk.inst];
+  const int j = wk.start + threadIdx.x;
+  double s = 0;
+  if (j < L.N) {
+    const long long g = L.voff + j;
+    const double di = (double)dinv[g];
+    const double vv = di * (double)y[g];
+    v[g] = (TV)vv;
+    s = vv * vv / di;
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+template <typename TV>
+void launch_hash_fill(hipStream_t st, const Work* w, int nb, const LInst* li, TV* v, unsigned seed) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL((k_hash_fill<TV>), GRID(nb), w, li, v, seed);
+}
+
+template <typename TV>
+void launch_mul_dinv(hipStream_t st, const Work* w, int nb, const LInst* li, const TV* dinv, const TV* y, TV* v,
+                     double* partial) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL((k_mul_dinv<TV>), GRID(nb), w, li, dinv, y, v, partial);
+}
+template void launch_hash_fill<float>(hipStream_t, const Work*, int, const LInst*, float*, unsigned);
+template void launch_hash_fill<double>(hipStream_t, const Work*, int, const LInst*, double*, unsigned);
+template void launch_mul_dinv<float>(hipStream_t, const Work*, int, const LInst*, const float*, const float*, float*,
+                                     double*);
+template void launch_mul_dinv<double>(hipStream_t, const Work*, int, const LInst*, const double*, const double*,
+                                      double*, double*);
+
+}  // namespace mpde

@@ -1,0 +1,77 @@
+// Launch wrappers of the solver kernels (defined in mpde_kernels.hip).
+#pragma once
+#include "mpde_internal.hpp"
+
+namespace mpde {
+
+hipError_t upload_stencils(const double w1[5][5], const double w2[5][5]);
+
+template <typename TA, typename TV, typename TC>
+void launch_gamma(int D, hipStream_t st, const Work* w, int nb, const LInst* li, CIdx ci, const TV* u,
+                  const TC* c, const TC* f, int sigma, TV* gam);
+template <typename TA, typename TV, typename TC>
+void launch_gather(int D, hipStream_t st, const Work* w, int nb, const LInst* li, CIdx ci, const TV* u,
+                   const TV* gam, const TC* c, const TC* bw, int sigma, int mode, TV* out, const TV* bvec,
+                   TV* x, TV* r, TV* d, const TV* dinv, int cheb_step, double* partial);
+template <typename TV, typename TC>
+void launch_diag(int D, hipStream_t st, const Work* w, int nb, const LInst* li, CIdx ci, const TC* c, TV* dinv);
+template <typename TV>
+void launch_cheb_init(hipStream_t st, const Work* w, int nb, const LInst* li, const TV* b, const TV* dinv, TV* x,
+                      TV* r, TV* d);
+template <typename TV>
+void launch_restrict(int D, hipStream_t st, const Work* w, int nb, const LInst* lf, const LInst* lc, const TV* rf,
+                     TV* rc);
+template <typename TV>
+void launch_prolong_add(int D, hipStream_t st, const Work* w, int nb, const LInst* lf, const LInst* lc,
+                        const TV* ec, TV* xf);
+template <typename TC>
+void launch_coarsen_coef(int D, hipStream_t st, const Work* w, int nb, const LInst* lf, const LInst* lc, int K,
+                         const TC* cf, TC* cc);
+void launch_set_unit(hipStream_t st, const LInst* probe, const int* col, int nprobe, double* U);
+void launch_gauss_jordan(hipStream_t st, int nmat, double* A, const long long* off, const int* n, int* fail);
+template <typename TV>
+void launch_convert_dense(hipStream_t st, const double* src, TV* dst, long long n);
+template <typename TV>
+void launch_dense_apply(hipStream_t st, const Work* w, int nb, const LInst* li, const TV* Sinv, const TV* r, TV* e);
+template <typename TA, typename TV>
+void launch_dot(hipStream_t st, const Work* w, int nb, const LInst* li, const TV* a, const TV* b, double* partial);
+void launch_finish_sum(hipStream_t st, const double* partial, const int* bstart, int B, double* out);
+void launch_pcg_scalars(hipStream_t st, int op, int B, int first, double tol2, double* rz_new, double* rz,
+                        double* beta, double* pq, double* alpha, double* rn2, double* r0n2, int* active,
+                        int* iters);
+template <typename TV>
+void launch_update_p(hipStream_t st, const Work* w, int nb, const LInst* li, const double* beta, const TV* z,
+                     TV* p);
+template <typename TV>
+void launch_update_xr(hipStream_t st, const Work* w, int nb, const LInst* li, const double* alpha, const TV* p,
+                      const TV* q, TV* x, TV* r, double* partial);
+template <typename TS, typename TD>
+void launch_copy_scale(hipStream_t st, const Work* w, int nb, const LInst* li, const TS* s, TD* d,
+                       const double* scale, int add);
+template <typename TV>
+void launch_fill(hipStream_t st, const Work* w, int nb, const LInst* li, TV* d, double v);
+template <typename TC>
+void launch_atd_norm(int D, hipStream_t st, const Work* w, int nb, const LInst* li, CIdx ci, const TC* c,
+                     const TC* f, const TC* bw, double* partial);
+template <typename TC, typename TO>
+void launch_output(int D, hipStream_t st, const Work* w, int nb, const LInst* li, CIdx ci, const double* u,
+                   const TC* c, const TC* f, TO* z, const long long* zoff);
+template <typename TC, typename TG>
+void launch_adj_local(int D, hipStream_t st, const Work* w, int nb, const LInst* li, CIdx ci, const TC* c,
+                      const TG* gz, const long long* zoff, double* vloc);
+template <typename TC, typename TG>
+void launch_adj_rhs(int D, hipStream_t st, const Work* w, int nb, const LInst* li, CIdx ci, const TC* c,
+                    const TG* gz, const long long* zoff, const double* vloc, double* ghat);
+template <typename TC, typename TG>
+void launch_adj_grad(int D, hipStream_t st, const Work* w, int nb, const LInst* li, CIdx ci, const TC* c,
+                     const TC* f, const double* ustar, const double* du, const TG* gz, const long long* zoff,
+                     TG* gc, TG* gf, TG* gw);
+template <typename T>
+void launch_nonfinite(hipStream_t st, const T* a, long long n, int* flag);
+template <typename TV>
+void launch_hash_fill(hipStream_t st, const Work* w, int nb, const LInst* li, TV* v, unsigned seed);
+template <typename TV>
+void launch_mul_dinv(hipStream_t st, const Work* w, int nb, const LInst* li, const TV* dinv, const TV* y, TV* v,
+                     double* partial);
+
+}  // namespace mpde

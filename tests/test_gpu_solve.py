@@ -1,0 +1,115 @@
+"""Parity of the HIP solve (through the C ABI) with the FP64 oracle.
+
+Bar: relative L2 error of z (all V planes, and the u plane) at most 1e-5 in
+FP32 and FP64, per instance; the normal-equation relative residual of the
+GPU answer, re-evaluated in FP64 with the oracle's assembled A, at most the
+requested tolerance."""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.helpers import gpu_solve, oracle_solve, rel, normal_relres
+
+pytestmark = pytest.mark.gpu
+
+IC, DIR, PER = ("dirichlet", "none"), ("dirichlet", "dirichlet"), ("periodic", "periodic")
+
+
+def _check(inst, zg, tol_err=1e-5):
+    zo, _ = oracle_solve(inst)
+    e_all, e_u = rel(zg, zo), rel(zg[0], zo[0])
+    assert e_all <= tol_err and e_u <= tol_err, (e_all, e_u)
+    return e_all
+
+
+def test_config1_fp64_parity():
+    inst = W.config1(0)
+    prob, zs, info = gpu_solve([inst], "f64", tol=1e-11)
+    assert info["status"][0] == 0, info
+    assert _check(inst, zs[0], 1e-8) <= 1e-8
+    assert normal_relres(inst, zs[0]) <= 1e-9
+
+
+def test_config1_default_tolerance():
+    inst = W.config1(0)
+    prob, zs, info = gpu_solve([inst], "f64")
+    assert info["code"] == 0 and info["relres"][0] <= 1e-6
+    assert normal_relres(inst, zs[0]) <= 1.0001e-6
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("shape,bc,mset", [
+    ((16, 16), (IC, DIR), (0, 1, 3, 4)),
+    ((12, 20), (DIR, DIR), (0, 1, 2, 3, 4)),
+    ((8, 8, 8), (IC, PER, PER), (0, 1, 3, 4, 5, 6)),
+    ((6, 10, 8), (IC, DIR, PER), (0, 1, 2, 3, 4, 5, 6)),
+])
+def test_quadratic_exact(dtype, shape, bc, mset):
+    inst = W.quadratic_exact(shape, bc, mset, seed=sum(shape))
+    prob, zs, info = gpu_solve([inst], dtype, tol=1e-10 if dtype == "f32" else 1e-13)
+    ze = np.stack([inst["exact"][v] for v in range(1 + 2 * len(shape))])
+    err = rel(zs[0], ze)
+    assert err <= (1e-5 if dtype == "f32" else 1e-8), err
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_config2_small_parity(dtype):
+    insts = [W.config2(i, shape=(8, 8, 8)) for i in range(3)]
+    prob, zs, info = gpu_solve(insts, dtype, tol=1e-10)
+    assert all(s == 0 for s in info["status"]), info
+    for inst, zg in zip(insts, zs):
+        _check(inst, zg)
+
+
+def test_config4_small_parity():
+    insts = [W.config4(i, shape=(8, 8, 8))[0] for i in range(2)]
+    prob, zs, info = gpu_solve(insts, "f32", tol=1e-10)
+    for inst, zg in zip(insts, zs):
+        _check(inst, zg)
+
+
+def test_ragged_batch_parity():
+    shapes = [(16, 16), (24, 48), (64, 16), (32, 24), (48, 64), (16, 32)]
+    insts = [W.config3(i, s) for i, s in enumerate(shapes)]
+    prob, zs, info = gpu_solve(insts, "f32", tol=1e-10)
+    assert all(s == 0 for s in info["status"]), info
+    for inst, zg in zip(insts, zs):
+        _check(inst, zg)
+    # same answer when solved alone (batching does not change results)
+    _, z1, _ = gpu_solve([insts[2]], "f32", tol=1e-10)
+    assert rel(z1[0], zs[2]) <= 1e-6
+
+
+def test_minimum_grid_no_coarsening():
+    inst = W.random_instance((5, 5), (IC, DIR), mset=(0, 1, 3, 4), seed=9)
+    prob, zs, info = gpu_solve([inst], "f64", tol=1e-12)
+    assert prob.levels(0) == [(5, 5)]
+    _check(inst, zs[0], 1e-9)
+
+
+def test_level_plan():
+    inst = W.config2(0, shape=(32, 64, 64))
+    prob, zs, info = gpu_solve([inst], "f32")
+    assert prob.levels(0) == [(32, 64, 64), (32, 32, 32), (32, 16, 16), (32, 8, 8), (32, 4, 4)]
+    inst = W.config3(0, (24, 48))
+    prob, zs, info = gpu_solve([inst], "f32")
+    assert prob.levels(0) == [(24, 48), (24, 24), (24, 12), (24, 6)]
+
+
+def test_nonfinite_input_rejected():
+    from paper_2502_18377_amd._native import MPDEError, MPDE_ERR_NONFINITE
+    inst = W.config1(0)
+    inst["coeff"] = inst["coeff"].copy()
+    inst["coeff"][1, 3, 3] = np.nan
+    with pytest.raises(MPDEError) as e:
+        gpu_solve([inst], "f32")
+    assert e.value.code == MPDE_ERR_NONFINITE
+
+
+def test_config2_full_size_residual():
+    # the benchmark workload: 64 instances of 32x64x64, FP32, default tolerance
+    insts = [W.config2(i) for i in range(64)]
+    prob, zs, info = gpu_solve(insts, "f32")
+    assert info["code"] == 0 and np.all(info["relres"] <= 1e-6), info
+    for b in (0, 37):   # FP64 residual of the GPU answer with the oracle's A
+        assert normal_relres(insts[b], zs[b]) <= 1.05e-6

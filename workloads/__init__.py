@@ -122,7 +122,7 @@ def config2(instance=0, shape=(32, 64, 64), config_id=2, dt=None):
     rng = rng_for(config_id, instance)
     nt, nx, ny = shape
     sx, sy = 1.0 / nx, 1.0 / ny
-    st = dt if dt is not None else sx * sx
+    st = dt if dt is not None else sx        # time step equal to the space step
     step = (st, sx, sy)
     SD = _fourier_field(rng, shape, step)
     Dc = 1.0 + 0.5 * SD / max(np.abs(SD).max(), 1e-30)
