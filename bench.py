@@ -1,0 +1,166 @@
+#!/usr/bin/env python3
+"""Benchmark of the NeuRLP-PDE solve on one MI355X.
+
+Workload: 64 instances of the 2D-space + time variable-coefficient
+diffusion-advection-reaction PDE on a 32(t) x 64(x) x 64(y) grid, periodic in
+space, Fourier-mode coefficient fields, Gaussian-random-field initial data,
+FP32, solved to a normal-equation relative residual of 1e-6 for every
+instance.  A step is one full pass of the hot path over the batch: build
+(coefficient coarsening, operator diagonals, Chebyshev intervals, dense
+coarsest inverses) plus the refined multigrid-PCG solve, with the inputs
+already resident in HBM.
+
+Prints one JSON line: solves/s, milliseconds per step, the roofline of the
+dominant finest-grid kernel (algorithmic bytes / event-timed duration of its
+launches inside the timed steps, against 8 TB/s), the HBM traffic of that
+kernel from committed rocprofv3 counter runs (null if the kernel source has
+changed since), and the FP64 oracle timed on the host CPU on a bounded
+sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PDE solves/sec to 1e-6 rel. residual, learned vs plain MG; stencil HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2502_18377_amd", "csrc", "mpde_kernels.hip")
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic_config2.json")
+
+
+def kernel_source_sha():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_for(kernel, launches_per_step_bytes):
+    """Counter-measured HBM bytes per launch for `kernel`, from a committed
+    summary of rocprofv3 FETCH_SIZE/WRITE_SIZE runs; null when absent or when
+    the kernel source differs from the one the counters were taken on."""
+    try:
+        with open(TRAFFIC) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha") != kernel_source_sha():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline(seconds=12.0, max_instances=8):
+    """FP64 oracle (saddle-point sparse LU, single-threaded SuperLU) on
+    instances of the same generator at 8x8x8 points: a direct factorisation
+    of a full 32x64x64 instance does not fit in host memory."""
+    import numpy as np
+    import workloads as W
+    from oracle.system import OracleProblem, assemble
+    from oracle.solve import solve_kkt
+    n, t0 = 0, time.perf_counter()
+    unknowns = 0
+    while n < max_instances and (time.perf_counter() - t0) < seconds:
+        inst = W.config2(1000 + n, shape=(8, 8, 8))
+        op = OracleProblem(**{k: inst[k] for k in ("shape", "step", "bc", "mset", "coeff", "rhs", "bc_values")})
+        A, d, _ = assemble(op)
+        solve_kkt(A, d)
+        unknowns += A.shape[1]
+        n += 1
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} instances of the same generator at 8x8x8 points ({unknowns // n} unknowns each), "
+                      f"FP64 saddle-point SuperLU, {dt:.1f} s; host has {os.cpu_count()} cores",
+            "unknowns_per_s": unknowns / dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="do not time kernels with events")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); instances of a batch are "
+              "independent, so a multi-GPU run would shard the batch with no communication.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2502_18377_amd.api import Problem, pack
+
+    dev = torch.device("cuda:0")
+    B = args.batch
+    insts = [W.config2(i) for i in range(B)]
+    pk = pack(insts, dtype=torch.float32, device=dev)
+    del insts
+    torch.cuda.synchronize()
+    prof = 0 if args.no_profile else 1
+
+    def step():
+        prob = Problem(pk["coeff"], pk["rhs"], pk["bc_values"], pk["shapes"], pk["steps"], pk["bc"], pk["mset"],
+                       profile=prof)
+        z, info = prob.solve()
+        ks = prob.kernel_stats() if prof else {}
+        prob.close()
+        return z, info, ks
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    kstat, iters, relres, outer, solve_s = {}, [], [], [], 0.0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        z, info, ks = step()
+        iters.append(info["iters"].mean())
+        outer.append(info["outer"].mean())
+        relres.append(float(info["relres"].max()))
+        solve_s += info["seconds"]
+        if info["code"] != 0:
+            raise SystemExit(f"solve did not converge: {info}")
+        for k, v in ks.items():
+            a = kstat.setdefault(k, dict(launches=0, ms=0.0, bytes=0.0))
+            for f in a:
+                a[f] += v[f]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1000 / args.steps
+    value = B * args.steps / (t1 - t0)
+
+    roof = None
+    if kstat:
+        name, k = max(kstat.items(), key=lambda kv: kv[1]["ms"])
+        per_launch_bytes = k["bytes"] / k["launches"]
+        per_launch_ms = k["ms"] / k["launches"]
+        achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": f"k_{name} (finest grid, FP32)", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic_for(name, per_launch_bytes),
+                "bytes_per_launch": per_launch_bytes, "us_per_launch": round(per_launch_ms * 1e3, 2),
+                "launches_per_step": k["launches"] / args.steps,
+                "kernels": {n: {"GB/s": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1),
+                                "ms_per_step": round(v["ms"] / args.steps, 3)} for n, v in kstat.items()}}
+
+    out = {"metric": METRIC, "value": round(value, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "64 instances of 2D-space+time diffusion-advection-reaction, 32(t)x64x64 "
+                                  "periodic, FP32, build+solve to 1e-6 normal-equation relative residual",
+                      "batch": B, "grid": [32, 64, 64], "solver": "plain multigrid-PCG"},
+           "solve_only_ms_per_step": round(solve_s * 1000 / args.steps, 3),
+           "mean_pcg_iters": round(float(np.mean(iters)), 2), "mean_outer_steps": round(float(np.mean(outer)), 2),
+           "max_relres": max(relres), "roofline": roof}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

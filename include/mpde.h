@@ -85,7 +85,11 @@ typedef struct {
                             non-periodic axis stops at >= 5 points */
   int32_t check_every;   /* Krylov iterations between host convergence checks (2) */
   int32_t max_levels;    /* cap on grid levels including the finest (16) */
-  int32_t reserved[8];
+  int32_t profile;       /* nonzero: time the finest-grid operator kernels of
+                            mpde_solve with HIP events (see mpde_kernel_stats) */
+  int32_t out_f64;       /* nonzero: mpde_solve writes z_out as FP64 (the FP64
+                            iterate) even for an MPDE_F32 problem (0) */
+  int32_t reserved[6];
 } mpde_options;
 
 /* Problem description (the encoder outputs of Eq. 2 with uniform steps). */
@@ -134,7 +138,7 @@ int mpde_default_options(mpde_options *o);
 int mpde_build(const mpde_desc *d, mpde_problem **out);
 
 /* Solve A^T A z = A^T d (Eq. 9) for every instance and write z* to z_out
- * (device, [sum_b V*N_b], dtype of the problem).  Keeps an internal copy of
+ * (device, [sum_b V*N_b], dtype of the problem, or FP64 if options.out_f64).  Keeps an internal copy of
  * u* for mpde_solve_adjoint.  info may be NULL.  Returns 0, or
  * MPDE_WARN_NOT_CONVERGED (z_out holds the best iterate), or an error. */
 int mpde_solve(mpde_problem *p, void *z_out, mpde_info *info);
@@ -155,6 +159,21 @@ void mpde_free(mpde_problem *p);
 
 /* Message of the last error on the calling thread ("" if none). */
 const char *mpde_last_error(void);
+
+/* Kernel statistics of the last mpde_solve run with options.profile set:
+ * one record per kernel family on the finest grid ("gamma": the per-point
+ * projection pass, "gather": the operator/smoother pass), with launches,
+ * summed device time in ms (HIP events on the problem's stream) and the
+ * algorithmic HBM bytes those launches must move (inputs read once, outputs
+ * written once).  Writes at most max records to out (host) and returns the
+ * number of records available (0 if p is NULL or profiling was off). */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double ms;
+  double bytes;
+} mpde_kstat;
+int mpde_kernel_stats(const mpde_problem *p, mpde_kstat *out, int32_t max);
 
 /* Grid levels planned for instance b (0 if p is NULL or b out of range);
  * if shapes is not NULL it receives levels*D points-per-axis values. */

@@ -13,7 +13,7 @@ MPDE_BC_NONE, MPDE_BC_DIRICHLET, MPDE_BC_PERIODIC = 0, 1, 2
 BC_CODES = {"none": MPDE_BC_NONE, "dirichlet": MPDE_BC_DIRICHLET, "periodic": MPDE_BC_PERIODIC}
 
 EXPORTS = ("mpde_default_options", "mpde_build", "mpde_solve", "mpde_solve_adjoint",
-           "mpde_free", "mpde_last_error", "mpde_levels")
+           "mpde_free", "mpde_last_error", "mpde_levels", "mpde_kernel_stats")
 
 
 class Options(ctypes.Structure):
@@ -21,7 +21,12 @@ class Options(ctypes.Structure):
                 ("max_outer", ctypes.c_int32), ("max_inner", ctypes.c_int32),
                 ("nu", ctypes.c_int32), ("coarse_min", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("max_levels", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 8)]
+                ("profile", ctypes.c_int32), ("out_f64", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+
+
+class KStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
 
 
 class Desc(ctypes.Structure):
@@ -71,6 +76,8 @@ def load():
     lib.mpde_last_error.restype = ctypes.c_char_p
     lib.mpde_levels.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     lib.mpde_levels.restype = ctypes.c_int
+    lib.mpde_kernel_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(KStat), ctypes.c_int32]
+    lib.mpde_kernel_stats.restype = ctypes.c_int
     _lib = lib
     return lib
 

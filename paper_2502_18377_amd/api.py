@@ -100,7 +100,10 @@ class Problem:
     def solve(self, out=None):
         """Return (z, info): z is the concatenated [V, N_b] blocks of all instances."""
         total = sum(self.npts)
-        z = out if out is not None else torch.empty(self.V * total, dtype=self.torch_dtype, device=self.device)
+        zdt = torch.float64 if self._opts.out_f64 else self.torch_dtype
+        z = out if out is not None else torch.empty(self.V * total, dtype=zdt, device=self.device)
+        if z.dtype != zdt or z.numel() != self.V * total:
+            raise ValueError("out has the wrong dtype or size")
         info, res = self._info()
         with torch.cuda.device(self.device):
             code = N.check(self._lib.mpde_solve(self._h, z.data_ptr(), ctypes.byref(info)))
@@ -123,6 +126,13 @@ class Problem:
                                                         ctypes.byref(info)))
         res["code"], res["seconds"] = code, info.seconds
         return gc, gf, gw, res
+
+    def kernel_stats(self):
+        """Finest-grid kernel timings of the last solve (options.profile=1)."""
+        arr = (N.KStat * 4)()
+        n = self._lib.mpde_kernel_stats(self._h, arr, 4)
+        return {arr[i].name.decode(): dict(launches=int(arr[i].launches), ms=arr[i].ms, bytes=arr[i].bytes)
+                for i in range(min(n, 4))}
 
     def levels(self, b=0):
         n = self._lib.mpde_levels(self._h, b, None)

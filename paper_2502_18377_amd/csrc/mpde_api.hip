@@ -99,6 +99,7 @@ T* dalloc(size_t n) {
 struct Table {
   std::vector<Work> h;
   std::vector<int> bstart;     // [B+1]
+  long long npts = 0;          // points covered
   Work* d = nullptr;
   int* d_bstart = nullptr;
   int nb() const { return (int)h.size(); }
@@ -136,9 +137,24 @@ struct mpde_problem {
   int *active = nullptr, *iters = nullptr, *flag = nullptr;
   void* Sinv = nullptr;                                    // TV dense inverses
   bool has_solution = false;
+  // profiling (options.profile): event pairs around finest-grid kernels
+  struct Rec { int kind; hipEvent_t a, b; double bytes; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used = 0;
+  mpde_kstat kst[2]{};
+  hipEvent_t ev() {
+    if (pool_used == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[pool_used++];
+  }
   std::vector<void*> owned;
   ~mpde_problem() {
     for (void* p : owned) (void)hipFree(p);
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
   }
   template <typename T>
   T* alloc(size_t n) {
@@ -160,11 +176,13 @@ void upload_table(mpde_problem* P, Table& t) {
 // Work items over the points of the selected instances (instance-major).
 void make_table(Table& t, const std::vector<LInst>& h, int B, const std::vector<int>& sel) {
   t.h.clear();
+  t.npts = 0;
   t.bstart.assign(B + 1, 0);
   for (int b = 0; b < B; ++b) {
     t.bstart[b] = (int)t.h.size();
     if (!sel[b]) continue;
     for (int s = 0; s < h[b].N; s += kBlock) t.h.push_back(Work{b, s});
+    t.npts += h[b].N;
   }
   t.bstart[B] = (int)t.h.size();
 }
@@ -187,21 +205,69 @@ struct Solver {
 
   void finish(const Table& t, double* out) { launch_finish_sum(st, P->partial, t.d_bstart, P->B, out); }
 
+  // Profiling of finest-grid kernels: kind 0 = gamma, 1 = gather.  Bytes are
+  // algorithmic: every input element read once, every output written once.
+  hipEvent_t pa = nullptr;
+  bool prof(int l) const { return P->opt.profile && l == 0; }
+  void pbeg(int l) {
+    if (!prof(l)) return;
+    pa = P->ev();
+    if (pa) (void)hipEventRecord(pa, st);
+  }
+  void pend(int l, int kind, const Table& t, int mode) {
+    if (!prof(l) || !pa) return;
+    hipEvent_t pb = P->ev();
+    if (!pb) return;
+    (void)hipEventRecord(pb, st);
+    const double p = sizeof(TV), K = P->K;
+    double per;
+    if (kind == 0) per = (2 + K) * p;                       // u, c in; gamma out
+    else if (mode == G_CHEB) per = (9 + K) * p;             // d, gamma, c, x, r, dinv in; x, r, d out
+    else if (mode == G_RESID) per = (7 + K) * p;            // u, gamma, c, b, dinv in; r, d out
+    else per = (3 + K) * p;                                 // u, gamma, c in; y out
+    P->recs.push_back({kind, pa, pb, per * (double)t.npts});
+    pa = nullptr;
+  }
+  void collect() {
+    if (!P->opt.profile) return;
+    HIPCHK(hipStreamSynchronize(st));
+    std::snprintf(P->kst[0].name, 32, "gamma");
+    std::snprintf(P->kst[1].name, 32, "gather");
+    for (auto& k : P->kst) { k.launches = 0; k.ms = 0; k.bytes = 0; }
+    for (auto& r : P->recs) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) continue;
+      P->kst[r.kind].launches += 1;
+      P->kst[r.kind].ms += ms;
+      P->kst[r.kind].bytes += r.bytes;
+    }
+    P->recs.clear();
+    P->pool_used = 0;
+  }
+
   // y = S u on level l for the instances of table t.
   void apply(int l, const Table& t, TV* u, TV* out, int mode, double* partial) {
     Level& L = P->lv[l];
+    pbeg(l);
     launch_gamma<TV, TV, TC>(D, st, t.d, t.nb(), L.d, P->ci, u, C(L.coef), C(P->f), 0, V(L.gam));
+    pend(l, 0, t, 0);
+    pbeg(l);
     launch_gather<TV, TV, TC>(D, st, t.d, t.nb(), L.d, P->ci, u, V(L.gam), C(L.coef), C(P->w), 0, mode, out,
                               nullptr, nullptr, nullptr, nullptr, nullptr, 0, partial);
+    pend(l, 1, t, mode);
   }
 
   void chebyshev(int l, TV* x, int nu) {
     Level& L = P->lv[l];
     const Table& t = L.smooth;
     for (int s = 0; s < nu; ++s) {
+      pbeg(l);
       launch_gamma<TV, TV, TC>(D, st, t.d, t.nb(), L.d, P->ci, V(L.dd), C(L.coef), C(P->f), 0, V(L.gam));
+      pend(l, 0, t, 0);
+      pbeg(l);
       launch_gather<TV, TV, TC>(D, st, t.d, t.nb(), L.d, P->ci, V(L.dd), V(L.gam), C(L.coef), C(P->w), 0, G_CHEB,
                                 nullptr, nullptr, x, V(L.r), V(L.dd), V(L.dinv), s, nullptr);
+      pend(l, 1, t, G_CHEB);
     }
   }
 
@@ -218,9 +284,13 @@ struct Solver {
     launch_restrict<TV>(D, st, Cc.all.d, Cc.all.nb(), L.d, Cc.d, V(L.r), V(Cc.b));
     vcycle(l + 1, V(Cc.b), V(Cc.x));
     launch_prolong_add<TV>(D, st, t.d, t.nb(), L.d, Cc.d, V(Cc.x), x);
+    pbeg(l);
     launch_gamma<TV, TV, TC>(D, st, t.d, t.nb(), L.d, P->ci, x, C(L.coef), C(P->f), 0, V(L.gam));
+    pend(l, 0, t, 0);
+    pbeg(l);
     launch_gather<TV, TV, TC>(D, st, t.d, t.nb(), L.d, P->ci, x, V(L.gam), C(L.coef), C(P->w), 0, G_RESID, V(L.r),
                               b, nullptr, nullptr, V(L.dd), V(L.dinv), 0, nullptr);
+    pend(l, 1, t, G_RESID);
     chebyshev(l, x, nu);
   }
 
@@ -682,8 +752,12 @@ void build_impl(mpde_problem* P, const mpde_desc* d) {
 template <typename TV, typename TC>
 int solve_impl(mpde_problem* P, void* z_out, mpde_info* info) {
   Solver<TV, TC> S(P);
+  P->recs.clear();
+  P->pool_used = 0;
   const int code = S.refine(false, P->u64, P->atd2, info);
-  S.template output<TC>((TC*)z_out);
+  S.collect();
+  if (P->opt.out_f64) S.template output<double>((double*)z_out);
+  else S.template output<TC>((TC*)z_out);
   HIPCHK(hipStreamSynchronize(P->st));
   P->has_solution = true;
   return code;
@@ -812,6 +886,13 @@ int mpde_solve_adjoint(mpde_problem* p, const void* g_z, void* grad_coeff, void*
 
 
 void mpde_free(mpde_problem* p) { delete p; }
+
+int mpde_kernel_stats(const mpde_problem* p, mpde_kstat* out, int32_t max) {
+  if (!p || !p->opt.profile) return 0;
+  for (int i = 0; i < 2 && i < max; ++i)
+    if (out) out[i] = p->kst[i];
+  return 2;
+}
 
 int mpde_levels(const mpde_problem* p, int32_t b, int32_t* shapes) {
   if (!p || b < 0 || b >= p->B) return 0;

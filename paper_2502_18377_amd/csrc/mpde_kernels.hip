@@ -1181,6 +1181,8 @@ template void launch_atd_norm<double>(int, hipStream_t, const Work*, int, const 
                                       const double*, const double*, double*);
 template void launch_output<float, float>(int, hipStream_t, const Work*, int, const LInst*, CIdx, const double*,
                                           const float*, const float*, float*, const long long*);
+template void launch_output<float, double>(int, hipStream_t, const Work*, int, const LInst*, CIdx, const double*,
+                                           const float*, const float*, double*, const long long*);
 template void launch_output<double, double>(int, hipStream_t, const Work*, int, const LInst*, CIdx,
                                             const double*, const double*, const double*, double*,
                                             const long long*);

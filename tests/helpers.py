@@ -5,6 +5,17 @@ import numpy as np
 from tests.conftest import to_oracle
 
 
+def as_dtype(inst, dtype):
+    """The instance with its data rounded to the GPU run's precision, so that
+    the oracle and the GPU solve the same problem."""
+    if dtype != "f32":
+        return inst
+    out = dict(inst)
+    for k in ("coeff", "rhs", "bc_values"):
+        out[k] = np.asarray(inst[k], np.float32).astype(np.float64)
+    return out
+
+
 def gpu_solve(instances, dtype="f32", **opts):
     import torch
     from paper_2502_18377_amd.api import Problem, pack
