@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = "PDE solves/sec to 1e-6 rel. residual, learned vs plain MG; stencil HBM GB/s"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_2502_18377_amd", "csrc", "mpde_kernels.hip")
-TRAFFIC = os.path.join(ROOT, "profiles", "traffic_config2.json")
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic_rd2d_64x32x64x64.json")
 
 
 def kernel_source_sha():
@@ -64,7 +64,7 @@ def cpu_baseline(seconds=12.0, max_instances=8):
     n, t0 = 0, time.perf_counter()
     unknowns = 0
     while n < max_instances and (time.perf_counter() - t0) < seconds:
-        inst = W.config2(1000 + n, shape=(8, 8, 8))
+        inst = W.reaction_diffusion_2d(1000 + n, shape=(8, 8, 8))
         op = OracleProblem(**{k: inst[k] for k in ("shape", "step", "bc", "mset", "coeff", "rhs", "bc_values")})
         A, d, _ = assemble(op)
         solve_kkt(A, d)
@@ -98,7 +98,7 @@ def main():
 
     dev = torch.device("cuda:0")
     B = args.batch
-    insts = [W.config2(i) for i in range(B)]
+    insts = [W.reaction_diffusion_2d(i) for i in range(B)]
     pk = pack(insts, dtype=torch.float32, device=dev)
     del insts
     torch.cuda.synchronize()

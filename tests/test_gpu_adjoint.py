@@ -34,10 +34,10 @@ def _oracle_grads(inst, gz):
 
 
 @pytest.mark.parametrize("dtype,inst_fn,bar", [
-    ("f64", lambda: W.config1(shape=(12, 16)), 1e-7),
-    ("f64", lambda: W.config3(5, (16, 24)), 1e-7),
-    ("f32", lambda: W.config4(1, shape=(8, 8, 8))[0], 1e-4),
-    ("f32", lambda: W.config2(2, shape=(8, 8, 8)), 1e-4),
+    ("f64", lambda: W.reaction_diffusion_1d(shape=(12, 16)), 1e-7),
+    ("f64", lambda: W.reaction_diffusion_1d_ragged(5, (16, 24)), 1e-7),
+    ("f32", lambda: W.advection_diffusion_2d(1, shape=(8, 8, 8))[0], 1e-4),
+    ("f32", lambda: W.reaction_diffusion_2d(2, shape=(8, 8, 8)), 1e-4),
 ])
 def test_adjoint_matches_oracle(dtype, inst_fn, bar):
     inst = as_dtype(inst_fn(), dtype)
@@ -54,7 +54,7 @@ def test_adjoint_matches_oracle(dtype, inst_fn, bar):
 
 def test_adjoint_vs_finite_differences_16cubed():
     # Advection-diffusion sub-case, loss = mean((u - target)^2) over the u plane.
-    inst, target = W.config4(3, shape=(16, 16, 16))
+    inst, target = W.advection_diffusion_2d(3, shape=(16, 16, 16))
     N = int(np.prod(inst["shape"]))
     V = 7
 
@@ -96,7 +96,7 @@ def test_autograd_function():
     import torch
     from paper_2502_18377_amd.api import pack
     from paper_2502_18377_amd.autograd import solve
-    inst = W.config1(shape=(10, 12))
+    inst = W.reaction_diffusion_1d(shape=(10, 12))
     pk = pack([inst], dtype=torch.float64, device="cuda")
     c = pk["coeff"].clone().requires_grad_(True)
     f = pk["rhs"].clone().requires_grad_(True)

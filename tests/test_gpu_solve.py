@@ -22,16 +22,16 @@ def _check(inst, zg, tol_err=1e-5):
     return e_all
 
 
-def test_config1_fp64_parity():
-    inst = W.config1(0)
+def test_rd1d_fp64_parity():
+    inst = W.reaction_diffusion_1d(0)
     prob, zs, info = gpu_solve([inst], "f64", tol=1e-11)
     assert info["status"][0] == 0, info
     assert _check(inst, zs[0], 1e-8) <= 1e-8
     assert normal_relres(inst, zs[0]) <= 1e-9
 
 
-def test_config1_default_tolerance():
-    inst = W.config1(0)
+def test_rd1d_default_tolerance():
+    inst = W.reaction_diffusion_1d(0)
     prob, zs, info = gpu_solve([inst], "f64")
     assert info["code"] == 0 and info["relres"][0] <= 1e-6
     assert normal_relres(inst, zs[0]) <= 1.0001e-6
@@ -55,16 +55,16 @@ def test_quadratic_exact(dtype, shape, bc, mset):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_config2_small_parity(dtype):
-    insts = [as_dtype(W.config2(i, shape=(8, 8, 8)), dtype) for i in range(3)]
+def test_rd2d_small_parity(dtype):
+    insts = [as_dtype(W.reaction_diffusion_2d(i, shape=(8, 8, 8)), dtype) for i in range(3)]
     prob, zs, info = gpu_solve(insts, dtype, tol=1e-10)
     assert all(s == 0 for s in info["status"]), info
     for inst, zg in zip(insts, zs):
         _check(inst, zg)
 
 
-def test_config4_small_parity():
-    insts = [as_dtype(W.config4(i, shape=(8, 8, 8))[0], "f32") for i in range(2)]
+def test_advdiff2d_small_parity():
+    insts = [as_dtype(W.advection_diffusion_2d(i, shape=(8, 8, 8))[0], "f32") for i in range(2)]
     prob, zs, info = gpu_solve(insts, "f32", tol=1e-10)
     for inst, zg in zip(insts, zs):
         _check(inst, zg)
@@ -72,7 +72,7 @@ def test_config4_small_parity():
 
 def test_ragged_batch_parity():
     shapes = [(16, 16), (24, 48), (64, 16), (32, 24), (48, 64), (16, 32)]
-    insts = [as_dtype(W.config3(i, s), "f32") for i, s in enumerate(shapes)]
+    insts = [as_dtype(W.reaction_diffusion_1d_ragged(i, s), "f32") for i, s in enumerate(shapes)]
     prob, zs, info = gpu_solve(insts, "f32", tol=1e-10)
     assert all(s == 0 for s in info["status"]), info
     for inst, zg in zip(insts, zs):
@@ -90,17 +90,17 @@ def test_minimum_grid_no_coarsening():
 
 
 def test_level_plan():
-    inst = W.config2(0, shape=(32, 64, 64))
+    inst = W.reaction_diffusion_2d(0, shape=(32, 64, 64))
     prob, zs, info = gpu_solve([inst], "f32")
     assert prob.levels(0) == [(32, 64, 64), (32, 32, 32), (32, 16, 16), (32, 8, 8), (32, 4, 4)]
-    inst = W.config3(0, (24, 48))
+    inst = W.reaction_diffusion_1d_ragged(0, (24, 48))
     prob, zs, info = gpu_solve([inst], "f32")
     assert prob.levels(0) == [(24, 48), (24, 24), (24, 12), (24, 6)]
 
 
 def test_nonfinite_input_rejected():
     from paper_2502_18377_amd._native import MPDEError, MPDE_ERR_NONFINITE
-    inst = W.config1(0)
+    inst = W.reaction_diffusion_1d(0)
     inst["coeff"] = inst["coeff"].copy()
     inst["coeff"][1, 3, 3] = np.nan
     with pytest.raises(MPDEError) as e:
@@ -108,12 +108,12 @@ def test_nonfinite_input_rejected():
     assert e.value.code == MPDE_ERR_NONFINITE
 
 
-def test_config2_full_size_residual():
+def test_rd2d_full_size_residual():
     # The benchmark workload: 64 instances of 32x64x64, FP32, default
     # tolerance.  The residual property is checked on the solver's FP64
     # iterate (out_f64): the FP32-rounded output carries a rounding floor of
     # about eps32 * ||A^T A|| ||z|| that no FP32 answer can go below.
-    insts = [as_dtype(W.config2(i), "f32") for i in range(64)]
+    insts = [as_dtype(W.reaction_diffusion_2d(i), "f32") for i in range(64)]
     prob, zs, info = gpu_solve(insts, "f32", out_f64=1)
     assert info["code"] == 0 and np.all(info["relres"] <= 1e-6), info["relres"].max()
     for b in (0, 37):   # FP64 residual of the GPU answer with the oracle's A

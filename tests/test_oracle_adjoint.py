@@ -44,7 +44,7 @@ def test_random_overdetermined_ls():
 
 
 def test_pde_gradients_vs_fd():
-    inst = W.config2(0, shape=(5, 6, 5), dt=0.1)
+    inst = W.reaction_diffusion_2d(0, shape=(5, 6, 5), dt=0.1)
     prob = to_oracle(inst)
     rng = np.random.default_rng(2)
     target = rng.standard_normal(prob.npoints * 7)

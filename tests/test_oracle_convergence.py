@@ -20,11 +20,11 @@ def _u_err(inst):
     return np.sqrt(np.mean((u - ue) ** 2)) / np.sqrt(np.mean(ue ** 2))
 
 
-def test_mms_config1_order():
+def test_mms_rd1d_order():
     # smooth coefficients so the observed order reflects the discretisation
     errs = []
     for n in (16, 32, 64):
-        inst = W.config1(shape=(n, n))
+        inst = W.reaction_diffusion_1d(shape=(n, n))
         T, X = np.meshgrid(np.linspace(0, 1, n), np.linspace(0, 1, n), indexing="ij")
         a = 0.5 + 0.3 * np.sin(2 * np.pi * X) * np.cos(np.pi * T)
         u = np.exp(-T) * np.sin(np.pi * X)
@@ -38,8 +38,8 @@ def test_mms_config1_order():
     assert order >= 1.5, (errs, order)
 
 
-def test_mms_config1_generator_converges():
-    errs = [_u_err(W.config1(shape=(n, n))) for n in (16, 32, 64)]
+def test_mms_rd1d_generator_converges():
+    errs = [_u_err(W.reaction_diffusion_1d(shape=(n, n))) for n in (16, 32, 64)]
     assert errs[0] > errs[1] > errs[2]
 
 

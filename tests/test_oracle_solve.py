@@ -49,8 +49,8 @@ def test_full_column_rank(shape, bc):
 
 
 def test_generators_full_rank():
-    for inst in (W.config1(shape=(6, 6)), W.config3(7, (6, 5)),
-                 W.config2(0, shape=(5, 6, 6)), W.config4(0, shape=(5, 6, 6))[0]):
+    for inst in (W.reaction_diffusion_1d(shape=(6, 6)), W.reaction_diffusion_1d_ragged(7, (6, 5)),
+                 W.reaction_diffusion_2d(0, shape=(5, 6, 6)), W.advection_diffusion_2d(0, shape=(5, 6, 6))[0]):
         A, _, _ = assemble(to_oracle(inst))
         s = np.linalg.svd(A.toarray(), compute_uv=False)
         assert s[-1] > 1e-10 * s[0]
@@ -83,7 +83,7 @@ def test_periodic_translation_invariance():
 
 
 def test_cg_reference_matches_direct():
-    inst = W.config1(shape=(12, 12))
+    inst = W.reaction_diffusion_1d(shape=(12, 12))
     A, d, _ = assemble(to_oracle(inst))
     zk = solve_kkt(A, d)[0]
     x, it, rel = cg_normal(A, A.T @ d, tol=1e-13, maxiter=50000)

@@ -20,15 +20,15 @@ An instance is a dict:
 All randomness comes from numpy.random.Generator(PCG64(seed)).
 
 Workloads (the five shapes of the benchmark suite):
-  config1   1D+time, 32x32, variable-coefficient reaction-advection-diffusion
+  reaction_diffusion_1d   1D+time, 32x32, variable-coefficient reaction-advection-diffusion
             with manufactured u* = exp(-t) sin(pi x); Dirichlet in x, initial
             data at t = 0.
-  config2   2D+time, 32x64x64, periodic space, Fourier-mode coefficient
+  reaction_diffusion_2d   2D+time, 32x64x64, periodic space, Fourier-mode coefficient
             fields, Gaussian-random-field initial data, zero source.
-  config3   config1 with each axis drawn from {16,24,32,48,64}.
-  config4   2D+time advection-diffusion with a divergence-free velocity from
+  reaction_diffusion_1d_ragged   reaction_diffusion_1d with each axis drawn from {16,24,32,48,64}.
+  advection_diffusion_2d   2D+time advection-diffusion with a divergence-free velocity from
             a 16-mode random streamfunction, 32x128x128.
-  config5   the config2 generator at 64x128x128.
+  reaction_diffusion_2d_large   the reaction_diffusion_2d generator at 64x128x128.
 """
 
 import numpy as np
@@ -38,8 +38,8 @@ VAR_NAMES3 = ("u", "u_t", "u_tt", "u_x", "u_xx", "u_y", "u_yy")
 RAGGED_SIZES = (16, 24, 32, 48, 64)
 
 
-def rng_for(config, instance):
-    return np.random.Generator(np.random.PCG64(1000 * config + instance))
+def rng_for(family, instance):
+    return np.random.Generator(np.random.PCG64(1000 * family + instance))
 
 
 def _box5(a, axis):
@@ -55,8 +55,8 @@ def _grid(shape, step):
     return np.meshgrid(*[np.arange(n) * s for n, s in zip(shape, step)], indexing="ij")
 
 
-# ----------------------------------------------------------------- config 1
-def config1(seed=None, shape=(32, 32), rng=None):
+# ------------------------------------------- 1D + time reaction-diffusion
+def reaction_diffusion_1d(seed=None, shape=(32, 32), rng=None):
     """u_t = a u_xx + b u_x + c u + f on [0,1]^2 (t, x), Dirichlet in x and
     initial data at t = 0, with f manufactured from u* = exp(-t) sin(pi x)."""
     rng = rng if rng is not None else rng_for(1, 0 if seed is None else seed)
@@ -79,17 +79,17 @@ def config1(seed=None, shape=(32, 32), rng=None):
                 exact={0: u, 1: ut, 2: u, 3: ux, 4: uxx})
 
 
-def config3_shapes(count=256, seed=0):
+def ragged_shapes(count=256, seed=0):
     rng = rng_for(3, 10_000 + seed)
     return [tuple(int(v) for v in rng.choice(RAGGED_SIZES, size=2)) for _ in range(count)]
 
 
-def config3(instance, shape):
-    """One ragged config-1 instance of the given (n_t, n_x)."""
-    return config1(shape=shape, rng=rng_for(3, instance))
+def reaction_diffusion_1d_ragged(instance, shape):
+    """One instance of the 1D + time workload of the given (n_t, n_x)."""
+    return reaction_diffusion_1d(shape=shape, rng=rng_for(3, instance))
 
 
-# ----------------------------------------------------------------- config 2
+# ------------------------------------------- 2D + time reaction-diffusion
 def _fourier_field(rng, shape, step, nmodes=8, kmax=3, time_modes=True):
     T, X, Y = _grid(shape, step)
     tf = max((shape[0] - 1) * step[0], 1e-30)
@@ -116,10 +116,10 @@ def gaussian_random_field(rng, shape, length=0.1):
     return g / sd if sd > 0 else g
 
 
-def config2(instance=0, shape=(32, 64, 64), config_id=2, dt=None):
+def reaction_diffusion_2d(instance=0, shape=(32, 64, 64), family=2, dt=None):
     """u_t = D (u_xx + u_yy) + v . grad u + r u on (t, x, y), x, y periodic on
     [0,1), initial data a Gaussian random field (length 0.1), zero source."""
-    rng = rng_for(config_id, instance)
+    rng = rng_for(family, instance)
     nt, nx, ny = shape
     sx, sy = 1.0 / nx, 1.0 / ny
     st = dt if dt is not None else sx        # time step equal to the space step
@@ -139,12 +139,12 @@ def config2(instance=0, shape=(32, 64, 64), config_id=2, dt=None):
                 mset=mset, coeff=coeff, rhs=np.zeros(shape), bc_values=omega)
 
 
-def config5(instance=0, shape=(64, 128, 128), dt=None):
-    return config2(instance, shape=shape, config_id=5, dt=dt)
+def reaction_diffusion_2d_large(instance=0, shape=(64, 128, 128), dt=None):
+    return reaction_diffusion_2d(instance, shape=shape, family=5, dt=dt)
 
 
-# ----------------------------------------------------------------- config 4
-def config4(instance=0, shape=(32, 128, 128), dt=None):
+# ------------------------------------------- 2D + time advection-diffusion
+def advection_diffusion_2d(instance=0, shape=(32, 128, 128), dt=None):
     """u_t + v . grad u = kappa (u_xx + u_yy) + f, v = (psi_y, -psi_x) from a
     16-mode random streamfunction scaled to max|v| = 1; kappa ~ U[0.005,0.05]
     per instance; f an 8-mode field; returns (instance, target field)."""
