@@ -686,6 +686,20 @@ void build_impl(mpde_problem* P, const mpde_desc* d) {
       }
       int st_ = 1;
       for (int a = D - 1; a >= 0; --a) { q.str[a] = st_; st_ *= q.n[a]; }
+      for (int a = 0; a < 3; ++a) {
+        // Gram block of the axis rows (T+, T-, C1, C2) for each row class.
+        for (int cls = 0; cls < 3; ++cls) {
+          const int tp = cls != 2, tm = cls != 1;
+          const double wT2 = q.wT[a] * q.wT[a];
+          const double g11 = wT2 * (tp + tm) + q.wC1[a] * q.wC1[a];
+          const double g12 = wT2 * (tp - tm) * 0.5;
+          const double g22 = wT2 * (tp + tm) * 0.25 + q.wC2[a] * q.wC2[a];
+          const double det = g11 * g22 - g12 * g12;
+          q.gi[a][cls][0] = g22 / det;
+          q.gi[a][cls][1] = -g12 / det;
+          q.gi[a][cls][2] = g11 / det;
+        }
+      }
       q.N = (int)N;
       q.coarsest = (l == P->nlev[b] - 1);
       q.ncoarsened = 0;

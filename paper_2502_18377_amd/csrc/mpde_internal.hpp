@@ -47,6 +47,10 @@ struct LInst {
   double is1[kMaxD];   // 1 / s
   double is2[kMaxD];   // 1 / s^2
   double wT[kMaxD], wC1[kMaxD], wC2[kMaxD];   // row weights per axis
+  // Inverse of the per-axis 2x2 Gram block G_a for the three row classes
+  // (0: both Taylor rows, 1: no T- (first point), 2: no T+ (last point)),
+  // entries (i11, i12, i22); filled by the host.
+  double gi[kMaxD][3][3];
   double cheb_theta, cheb_delta;              // Chebyshev interval of D^-1 S
   long long voff;      // offset (points) of this instance in level vectors
   long long coff;      // offset (elements) of its coefficient block (K planes)

@@ -106,14 +106,12 @@ __device__ __forceinline__ AxisRows<TA, TV> axis_rows(const LInst& L, int a, con
 // 2x2 inverse of the per-axis Gram block G_a (depends on tp, tm and weights).
 template <typename TA>
 __device__ __forceinline__ void ginv(const LInst& L, int a, int tp, int tm, TA& i11, TA& i12, TA& i22) {
-  const TA wT2 = (TA)(L.wT[a] * L.wT[a]);
-  const TA t = (TA)(tp + tm), dlt = (TA)(tp - tm);
-  const TA g11 = wT2 * t + (TA)(L.wC1[a] * L.wC1[a]);
-  const TA g12 = wT2 * dlt * (TA)0.5;
-  const TA g22 = wT2 * t * (TA)0.25 + (TA)(L.wC2[a] * L.wC2[a]);
-  const TA inv = (TA)1 / (g11 * g22 - g12 * g12);
-  i11 = g22 * inv; i12 = -g12 * inv; i22 = g11 * inv;
+  const int cls = tm ? (tp ? 0 : 2) : 1;
+  i11 = (TA)L.gi[a][cls][0]; i12 = (TA)L.gi[a][cls][1]; i22 = (TA)L.gi[a][cls][2];
 }
+
+// Periodic wrap for |o| <= n (no integer division).
+__device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 // Scaled equation-row coefficients of axis a's derivative unknowns at p.
 template <typename TA, typename TC>
@@ -242,11 +240,45 @@ __global__ void __launch_bounds__(kBlock) k_gather(const Work* __restrict__ work
     for (int a = 0; a < D; ++a) {
       const int n = L.n[a], st = L.str[a], per = L.per[a], ia = ic[a];
       const TA wT = (TA)L.wT[a], wC1 = (TA)L.wC1[a], wC2 = (TA)L.wC2[a];
+      if ((per && n >= 5) || (ia >= 5 && ia <= n - 6)) {
+        // Interior fast path: the five candidate rows i = j-2..j+2 are all
+        // centred rows with both Taylor rows (G_a diagonal), and no edge row
+        // reaches j; the 9-point line of u around j covers every window.
+        TA ul[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) ul[k] = (k == 4) ? uj : (TA)U[nbr(j, ia, k - 4, n, st, per)];
+        const TA ig1 = (TA)L.gi[a][0][0], ig2 = (TA)L.gi[a][0][2];
+        const int k1 = ci.k[1 + 2 * a], k2 = ci.k[2 + 2 * a];
+#pragma unroll
+        for (int o = -2; o <= 2; ++o) {
+          const long long pi = (o == 0) ? (long long)j : nbr(j, ia, o, n, st, per);
+          const TA rTp = wT * (ul[o + 4] - ul[o + 5]);
+          const TA rTm = wT * (ul[o + 4] - ul[o + 3]);
+          TA s1 = 0, s2 = 0;
+#pragma unroll
+          for (int m = 0; m < 5; ++m) {
+            s1 += W1<TA>(2, m) * ul[o + 2 + m];
+            s2 += W2<TA>(2, m) * ul[o + 2 + m];
+          }
+          const TA rC1 = -wC1 * s1, rC2 = -wC2 * s2;
+          const TA ca = k1 < 0 ? (TA)0 : (TA)c[L.coff + (long long)k1 * L.N + pi] * (TA)L.is1[a];
+          const TA caa = k2 < 0 ? (TA)0 : (TA)c[L.coff + (long long)k2 * L.N + pi] * (TA)L.is2[a];
+          const TA g = (TA)G[pi];
+          const TA x1 = -ig1 * (wT * (rTp - rTm) + wC1 * rC1 + ca * g);
+          const TA x2 = -ig2 * (wT * (rTp + rTm) * (TA)0.5 + wC2 * rC2 + caa * g);
+          const TA qC1 = rC1 + wC1 * x1, qC2 = rC2 + wC2 * x2;
+          y -= wC1 * W1<TA>(2, 2 - o) * qC1 + wC2 * W2<TA>(2, 2 - o) * qC2;
+          if (o == 0) y += wT * (rTp + wT * (x1 + (TA)0.5 * x2) + rTm + wT * (-x1 + (TA)0.5 * x2));
+          else if (o == -1) y -= wT * (rTp + wT * (x1 + (TA)0.5 * x2));
+          else if (o == 1) y -= wT * (rTm + wT * (-x1 + (TA)0.5 * x2));
+        }
+        continue;
+      }
       const int R = per ? 2 : 4;
       for (int o = -R; o <= R; ++o) {       // candidate row owner i = j + o e_a
         const int ii = ia + o;
         if (!per && (ii < 0 || ii >= n)) continue;
-        const int iw = per ? ((ii % n) + n) % n : ii;
+        const int iw = per ? wrap(ii, n) : ii;
         int tp, tm, wp;
         axis_class(iw, n, per, tp, tm, wp);
         const int k = wp - o;               // position of j in row i's window
@@ -358,7 +390,7 @@ __global__ void __launch_bounds__(kBlock) k_diag(const Work* __restrict__ work, 
       if (o == 0) continue;
       const int ii = ia + o;
       if (!per && (ii < 0 || ii >= n)) continue;
-      const int iw = per ? ((ii % n) + n) % n : ii;
+      const int iw = per ? wrap(ii, n) : ii;
       if (per && n == 4 && o == -2) continue;      // same owner as o = +2, merged below
       int tp, tm, wp;
       axis_class(iw, n, per, tp, tm, wp);
@@ -623,14 +655,16 @@ __global__ void __launch_bounds__(kBlock) k_dot(const Work* __restrict__ work, c
   if (threadIdx.x == 0) partial[blockIdx.x] = v;
 }
 
-// Per-instance fixed-order sum of block partials: out[b] = sum partial[bs[b]..bs[b+1]).
-__global__ void k_finish_sum(const double* __restrict__ partial, const int* __restrict__ bstart, int B,
-                             double* __restrict__ out) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
+// Per-instance fixed-order sum of block partials: out[b] = sum partial[bs[b]..bs[b+1]);
+// one block per instance, strided per-thread sums then a fixed tree.
+__global__ void __launch_bounds__(kBlock) k_finish_sum(const double* __restrict__ partial,
+                                                       const int* __restrict__ bstart, int B,
+                                                       double* __restrict__ out) {
+  const int b = blockIdx.x;
   double s = 0;
-  for (int i = bstart[b]; i < bstart[b + 1]; ++i) s += partial[i];
-  out[b] = s;
+  for (int i = bstart[b] + threadIdx.x; i < bstart[b + 1]; i += kBlock) s += partial[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) out[b] = s;
 }
 
 // Scalar updates of PCG, one thread per instance.
@@ -876,7 +910,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_rhs(const Work* __restrict__ wor
     for (int o = -R; o <= R; ++o) {
       const int ii = ia + o;
       if (!per && (ii < 0 || ii >= n)) continue;
-      const int iw = per ? ((ii % n) + n) % n : ii;
+      const int iw = per ? wrap(ii, n) : ii;
       int tp, tm, wp;
       axis_class(iw, n, per, tp, tm, wp);
       const int k = wp - o;
@@ -1050,7 +1084,7 @@ void launch_dot(hipStream_t st, const Work* w, int nb, const LInst* li, const TV
 }
 
 void launch_finish_sum(hipStream_t st, const double* partial, const int* bstart, int B, double* out) {
-  hipLaunchKernelGGL(k_finish_sum, dim3((B + 255) / 256), dim3(256), 0, st, partial, bstart, B, out);
+  hipLaunchKernelGGL(k_finish_sum, dim3(B), dim3(kBlock), 0, st, partial, bstart, B, out);
 }
 
 void launch_pcg_scalars(hipStream_t st, int op, int B, int first, double tol2, double* rz_new, double* rz,
