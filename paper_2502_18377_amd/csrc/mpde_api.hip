@@ -110,6 +110,8 @@ struct Level {
   LInst* d = nullptr;
   long long npts = 0;          // total points of this level
   Table all, smooth, dense;    // all instances / non-coarsest / coarsest (rows)
+  std::vector<int> cinst;      // instances whose coarsest level is this one
+  int* d_cinst = nullptr;
   void* coef = nullptr;        // TC [K planes per instance]
   void *x = nullptr, *r = nullptr, *dd = nullptr, *b = nullptr, *gam = nullptr, *dinv = nullptr;
 };
@@ -275,7 +277,7 @@ struct Solver {
   void vcycle(int l, TV* b, TV* x) {
     Level& L = P->lv[l];
     const int nu = P->opt.nu;
-    if (L.dense.nb() > 0) launch_dense_apply<TV>(st, L.dense.d, L.dense.nb(), L.d, V(P->Sinv), b, x);
+    if (!L.cinst.empty()) launch_bb_solve<TV>(st, (int)L.cinst.size(), L.d_cinst, L.d, V(P->Sinv), b, x);
     if (L.smooth.nb() == 0) return;
     const Table& t = L.smooth;
     launch_cheb_init<TV>(st, t.d, t.nb(), L.d, b, V(L.dinv), x, V(L.r), V(L.dd));
@@ -436,72 +438,81 @@ struct Solver {
     }
   }
 
-  // Dense inverses of the coarsest operators: probe S with unit vectors (one
-  // virtual instance per column), invert in FP64 by Gauss-Jordan, store in TV.
+  // Coarsest-grid factors.  The re-discretised operator of each instance's
+  // coarsest level is block banded in time (plane blocks, |t - t'| <= 4).
+  // Its lower band blocks are probed with time-coloured vectors (9 colours
+  // per plane point), factored by a block Cholesky in FP64 (diagonal blocks
+  // kept as inverses) and stored in the working precision for the block
+  // forward/backward substitution of every V-cycle.
   void build_dense() {
     const int B = P->B;
-    std::vector<long long> doff(B, -1), moff;
-    std::vector<int> mn;
-    long long tot = 0, totsq = 0;
+    constexpr int NCOL = 9;
+    std::vector<long long> boff(B, 0), yoff(B, 0);
+    long long totb = 0, toty = 0;
+    std::vector<int> Tn(B), mn(B);
     for (int b = 0; b < B; ++b) {
-      const int lc = P->nlev[b] - 1;
-      const int n = P->lv[lc].h[b].N;
-      doff[b] = totsq;
-      totsq += (long long)n * n;
+      const LInst& q = P->lv[P->nlev[b] - 1].h[b];
+      Tn[b] = q.n[0];
+      mn[b] = q.N / q.n[0];
+      boff[b] = totb; totb += (long long)Tn[b] * 5 * mn[b] * mn[b];
+      yoff[b] = toty; toty += (long long)std::min(q.n[0], NCOL) * mn[b] * q.N;
     }
-    (void)tot;
-    double* U = dalloc<double>(totsq);
-    double* GM = dalloc<double>(totsq);
-    double* SC = dalloc<double>(totsq);
+    double* LB = dalloc<double>(totb);
+    double* U = dalloc<double>(toty);
+    double* GM = dalloc<double>(toty);
+    double* Y = dalloc<double>(toty);
     int* dfail = dalloc<int>(B);
-    struct Free { std::vector<void*> v; ~Free() { for (void* p : v) (void)hipFree(p); } } fr{{U, GM, SC, dfail}};
-    HIPCHK(hipMemsetAsync(U, 0, totsq * sizeof(double), st));
+    struct Free { std::vector<void*> v; ~Free() { for (void* p : v) (void)hipFree(p); } } fr{{LB, U, GM, Y, dfail}};
+    HIPCHK(hipMemsetAsync(LB, 0, totb * sizeof(double), st));
+    HIPCHK(hipMemsetAsync(U, 0, toty * sizeof(double), st));
     HIPCHK(hipMemsetAsync(dfail, 0, B * sizeof(int), st));
+    auto upload = [&](const void* h, size_t bytes) {
+      void* d = dalloc<char>(bytes);
+      fr.v.push_back(d);
+      HIPCHK(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, st));
+      return d;
+    };
     for (int l = 0; l < (int)P->lv.size(); ++l) {
       Level& L = P->lv[l];
-      std::vector<LInst> vi;
-      std::vector<int> col;
+      std::vector<LInst> vq;
+      std::vector<int> pc, ps;
+      std::vector<long long> bo;
       std::vector<Work> wk;
+      int ncolor = -1;
       for (int b = 0; b < B; ++b) {
         if (L.h[b].N == 0 || !L.h[b].coarsest) continue;
-        const int n = L.h[b].N;
-        for (int c = 0; c < n; ++c) {
-          LInst q = L.h[b];
-          q.voff = doff[b] + (long long)c * n;
-          const int id = (int)vi.size();
-          vi.push_back(q);
-          col.push_back(c);
-          for (int s = 0; s < n; s += kBlock) wk.push_back(Work{id, s});
-        }
+        const int n = L.h[b].N, plane = mn[b], nc = std::min(L.h[b].n[0], NCOL);
+        if (ncolor >= 0 && nc != ncolor)
+          throw std::string("mixed time-axis lengths below 9 on one coarsest level are not supported");
+        ncolor = nc;
+        for (int c = 0; c < nc; ++c)
+          for (int sp = 0; sp < plane; ++sp) {
+            const int id = (int)vq.size();
+            LInst q = L.h[b];
+            q.voff = yoff[b] + (long long)(c * plane + sp) * n;
+            vq.push_back(q); pc.push_back(c); ps.push_back(sp); bo.push_back(boff[b]);
+            for (int s0 = 0; s0 < n; s0 += kBlock) wk.push_back(Work{id, s0});
+          }
       }
-      if (vi.empty()) continue;
-      LInst* dvi = dalloc<LInst>(vi.size());
-      int* dcol = dalloc<int>(col.size());
-      Work* dwk = dalloc<Work>(wk.size());
-      fr.v.push_back(dvi); fr.v.push_back(dcol); fr.v.push_back(dwk);
-      HIPCHK(hipMemcpyAsync(dvi, vi.data(), vi.size() * sizeof(LInst), hipMemcpyHostToDevice, st));
-      HIPCHK(hipMemcpyAsync(dcol, col.data(), col.size() * sizeof(int), hipMemcpyHostToDevice, st));
-      HIPCHK(hipMemcpyAsync(dwk, wk.data(), wk.size() * sizeof(Work), hipMemcpyHostToDevice, st));
-      launch_set_unit(st, dvi, dcol, (int)vi.size(), U);
-      launch_gamma<double, double, TC>(D, st, dwk, (int)wk.size(), dvi, P->ci, U, C(L.coef), C(P->f), 0, GM);
-      launch_gather<double, double, TC>(D, st, dwk, (int)wk.size(), dvi, P->ci, U, GM, C(L.coef), C(P->w), 0,
-                                        G_STORE, SC, nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr);
+      if (vq.empty()) continue;
+      auto* dvq = (LInst*)upload(vq.data(), vq.size() * sizeof(LInst));
+      auto* dpc = (int*)upload(pc.data(), pc.size() * sizeof(int));
+      auto* dps = (int*)upload(ps.data(), ps.size() * sizeof(int));
+      auto* dbo = (long long*)upload(bo.data(), bo.size() * sizeof(long long));
+      auto* dwk = (Work*)upload(wk.data(), wk.size() * sizeof(Work));
+      launch_set_probe(st, dvq, dpc, dps, (int)vq.size(), ncolor, U);
+      launch_gamma<double, double, TC>(D, st, dwk, (int)wk.size(), dvq, P->ci, U, C(L.coef), C(P->f), 0, GM);
+      launch_gather<double, double, TC>(D, st, dwk, (int)wk.size(), dvq, P->ci, U, GM, C(L.coef), C(P->w), 0,
+                                        G_STORE, Y, nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr);
+      launch_extract_band(st, dwk, (int)wk.size(), dvq, dpc, dps, dbo, ncolor, Y, LB);
       HIPCHK(hipStreamSynchronize(st));
     }
-    std::vector<long long> offs;
-    std::vector<int> ns;
-    for (int b = 0; b < B; ++b) {
-      offs.push_back(doff[b]);
-      ns.push_back(P->lv[P->nlev[b] - 1].h[b].N);
-    }
-    long long* doffs = dalloc<long long>(B);
-    int* dns = dalloc<int>(B);
-    fr.v.push_back(doffs); fr.v.push_back(dns);
-    HIPCHK(hipMemcpyAsync(doffs, offs.data(), B * sizeof(long long), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(dns, ns.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
-    launch_gauss_jordan(st, B, SC, doffs, dns, dfail);
-    P->Sinv = P->alloc<TV>(totsq);
-    launch_convert_dense<TV>(st, SC, V(P->Sinv), totsq);
+    auto* dboff = (long long*)upload(boff.data(), B * sizeof(long long));
+    auto* dT = (int*)upload(Tn.data(), B * sizeof(int));
+    auto* dm = (int*)upload(mn.data(), B * sizeof(int));
+    launch_bb_factor(st, B, LB, dboff, dT, dm, dfail);
+    P->Sinv = P->alloc<TV>(totb);
+    launch_convert_dense<TV>(st, LB, V(P->Sinv), totb);
     std::vector<int> hf(B);
     HIPCHK(hipMemcpyAsync(hf.data(), dfail, B * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -510,10 +521,14 @@ struct Solver {
                                    " is not positive definite (rank-deficient problem?)");
     for (int l = 0; l < (int)P->lv.size(); ++l) {
       Level& L = P->lv[l];
-      bool any = false;
+      L.cinst.clear();
       for (int b = 0; b < B; ++b)
-        if (L.h[b].N && L.h[b].coarsest) { L.h[b].doff = doff[b]; any = true; }
-      if (any) HIPCHK(hipMemcpyAsync(L.d, L.h.data(), L.h.size() * sizeof(LInst), hipMemcpyHostToDevice, st));
+        if (L.h[b].N && L.h[b].coarsest) { L.h[b].doff = boff[b]; L.cinst.push_back(b); }
+      if (!L.cinst.empty()) {
+        HIPCHK(hipMemcpyAsync(L.d, L.h.data(), L.h.size() * sizeof(LInst), hipMemcpyHostToDevice, st));
+        L.d_cinst = P->alloc<int>(L.cinst.size());
+        HIPCHK(hipMemcpyAsync(L.d_cinst, L.cinst.data(), L.cinst.size() * sizeof(int), hipMemcpyHostToDevice, st));
+      }
     }
     HIPCHK(hipStreamSynchronize(st));
   }
@@ -624,9 +639,13 @@ void plan(const int* n0, const double* s0, int D, const int* per, const mpde_opt
   for (int a = 0; a < D; ++a) { n[a] = n0[a]; s[a] = s0[a]; }
   shapes = {n}; steps = {s}; halv = {k};
   while ((int)shapes.size() < opt.max_levels) {
+    long long N = 1;
+    for (int a = 0; a < D; ++a) N *= n[a];
     bool any = false;
     for (int a = 1; a < D; ++a) {
-      const int lim = per[a] ? opt.coarse_min : 5;
+      // periodic axes stop at coarse_min, or continue to 4 while the grid is
+      // still too large for the dense coarsest solve; others stop at >= 5
+      const int lim = per[a] ? (N > kMaxDense ? std::min(4, opt.coarse_min) : opt.coarse_min) : 5;
       if (n[a] % 2 == 0 && n[a] / 2 >= lim) { n[a] /= 2; s[a] *= 2; k[a] += 1; any = true; }
     }
     if (!any) break;
@@ -653,6 +672,8 @@ void build_impl(mpde_problem* P, const mpde_desc* d) {
     maxl = std::max(maxl, P->nlev[b]);
     long long Nc = 1;
     for (int a = 0; a < D; ++a) Nc *= P->lshape[b].back()[a];
+    if (Nc / P->lshape[b].back()[0] > 64)
+      throw std::string("coarsest spatial plane of instance " + std::to_string(b) + " exceeds 64 points");
     if (Nc > kMaxDense)
       throw std::string("coarsest grid of instance " + std::to_string(b) + " has " + std::to_string(Nc) +
                         " points; the dense coarsest solve supports at most " + std::to_string(kMaxDense) +
@@ -816,7 +837,7 @@ int mpde_default_options(mpde_options* o) {
   o->max_outer = 30;
   o->max_inner = 200;
   o->nu = 2;
-  o->coarse_min = 4;
+  o->coarse_min = 8;
   o->check_every = 2;
   o->max_levels = 16;
   return MPDE_OK;

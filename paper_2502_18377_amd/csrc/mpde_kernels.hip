@@ -575,6 +575,250 @@ __global__ void __launch_bounds__(kBlock) k_set_unit(const LInst* __restrict__ p
   if (q < nprobe) U[probe[q].voff + col[q]] = 1.0;
 }
 
+// Time-coloured probe vectors for the coarsest operator, whose couplings
+// reach at most 4 time steps: probe (c, s) has ones at the points (t, s) with
+// t = c (mod 9), so every operator column is recovered from one probe.
+__global__ void __launch_bounds__(kBlock) k_set_probe(const LInst* __restrict__ probe, const int* __restrict__ pc,
+                                                      const int* __restrict__ ps, int nprobe, int ncolor,
+                                                      double* __restrict__ U) {
+  const int q = blockIdx.x;
+  const LInst& L = probe[q];
+  const int m = L.N / L.n[0];
+  for (int t = pc[q] + (int)threadIdx.x * ncolor; t < L.n[0]; t += (int)blockDim.x * ncolor)
+    U[L.voff + (long long)t * m + ps[q]] = 1.0;
+}
+
+// Scatter probe responses into the dense column-major matrix:
+// S[i][j] = Y_(c(j), s(j))[i] for |t(i) - t(j)| <= 4.
+__global__ void __launch_bounds__(kBlock) k_extract_probe(const Work* __restrict__ work, const LInst* __restrict__ probe,
+                                                          const int* __restrict__ pc, const int* __restrict__ ps,
+                                                          const long long* __restrict__ dout, int ncolor,
+                                                          const double* __restrict__ Y, double* __restrict__ S) {
+  const Work wk = work[blockIdx.x];
+  const LInst& L = probe[wk.inst];
+  const int i = wk.start + threadIdx.x;
+  if (i >= L.N) return;
+  const int m = L.N / L.n[0];
+  const int tr = i / m;
+  const int c = pc[wk.inst], sc = ps[wk.inst];
+  // the column time t = c (mod ncolor) within [tr - 4, tr + 4]; with a time
+  // axis no longer than the colour count each probe is a single time step
+  int t;
+  if (L.n[0] <= ncolor) {
+    t = c;
+  } else {
+    const int lo = tr - 4;
+    t = lo + ((c - lo) % ncolor + ncolor) % ncolor;
+    if (t > tr + 4 || t >= L.n[0] || t < 0) return;
+  }
+  const long long j = (long long)t * m + sc;
+  S[dout[wk.inst] + j * L.N + i] = Y[L.voff + i];
+}
+
+// ------------------------------------------------ block-banded coarsest solve
+// The coarsest operator, in time-major order, is block banded: blocks are
+// spatial planes of m <= 64 points and only blocks with |t - t'| <= 4 are
+// nonzero.  Lower blocks are stored per instance as Lb[t][k] = block
+// (t, t - k), k = 0..4, row-major m x m.  The factor keeps the off-diagonal
+// blocks of L and the inverses of its diagonal blocks.
+constexpr int kBBMax = 64;
+
+__device__ __forceinline__ long long bb_at(long long base, int t, int k, int m) {
+  return base + ((long long)t * 5 + k) * m * m;
+}
+
+// Probe responses into the lower band blocks.
+__global__ void __launch_bounds__(kBlock) k_extract_band(const Work* __restrict__ work, const LInst* __restrict__ probe,
+                                                         const int* __restrict__ pc, const int* __restrict__ ps,
+                                                         const long long* __restrict__ bout, int ncolor,
+                                                         const double* __restrict__ Y, double* __restrict__ Lb) {
+  const Work wk = work[blockIdx.x];
+  const LInst& L = probe[wk.inst];
+  const int i = wk.start + threadIdx.x;
+  if (i >= L.N) return;
+  const int m = L.N / L.n[0];
+  const int tr = i / m, sr = i - tr * m;
+  const int c = pc[wk.inst], sc = ps[wk.inst];
+  int t;
+  if (L.n[0] <= ncolor) {
+    t = c;
+  } else {
+    const int lo = tr - 4;
+    t = lo + ((c - lo) % ncolor + ncolor) % ncolor;
+    if (t > tr + 4 || t >= L.n[0] || t < 0) return;
+  }
+  const int k = tr - t;
+  if (k < 0 || k > 4) return;
+  Lb[bb_at(bout[wk.inst], tr, k, m) + (long long)sr * m + sc] = Y[L.voff + i];
+}
+
+// Block Cholesky, one block of threads per instance, FP64.
+__global__ void __launch_bounds__(kBlock) k_bb_factor(double* __restrict__ Lb, const long long* __restrict__ boff,
+                                                      const int* __restrict__ Tn, const int* __restrict__ mn,
+                                                      int* __restrict__ fail) {
+  const long long base = boff[blockIdx.x];
+  const int T = Tn[blockIdx.x], m = mn[blockIdx.x];
+  __shared__ double Dg[kBBMax][kBBMax + 1];
+  __shared__ double Di[kBBMax][kBBMax + 1];
+  __shared__ double Ab[kBBMax][kBBMax + 1];
+  const int tid = threadIdx.x;
+  for (int j = 0; j < T; ++j) {
+    double* Bjj = Lb + bb_at(base, j, 0, m);
+    for (int e = tid; e < m * m; e += blockDim.x) Dg[e / m][e % m] = Bjj[e];
+    __syncthreads();
+    // unblocked Cholesky of the diagonal block (lower)
+    for (int k = 0; k < m; ++k) {
+      if (tid == 0) {
+        const double a = Dg[k][k];
+        if (!(a > 0)) fail[blockIdx.x] = 1;
+        Dg[k][k] = a > 0 ? sqrt(a) : 1.0;
+      }
+      __syncthreads();
+      const double piv = Dg[k][k];
+      for (int r = k + 1 + tid; r < m; r += blockDim.x) Dg[r][k] /= piv;
+      __syncthreads();
+      for (int e = tid; e < (m - k - 1) * (m - k - 1); e += blockDim.x) {
+        const int r = k + 1 + e / (m - k - 1), cc = k + 1 + e % (m - k - 1);
+        if (cc <= r) Dg[r][cc] -= Dg[r][k] * Dg[cc][k];
+      }
+      __syncthreads();
+    }
+    // inverse of the lower-triangular factor: column c by forward substitution
+    for (int cc = tid; cc < m; cc += blockDim.x) {
+      for (int r = 0; r < m; ++r) {
+        double acc = (r == cc) ? 1.0 : 0.0;
+        if (r < cc) { Di[r][cc] = 0.0; continue; }
+        for (int q = cc; q < r; ++q) acc -= Dg[r][q] * Di[q][cc];
+        Di[r][cc] = acc / Dg[r][r];
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < m * m; e += blockDim.x) Bjj[e] = Di[e / m][e % m];
+    __syncthreads();
+    // off-diagonal blocks of column j: L_ij = B_ij * L_jj^-T
+    const int ie = min(T - 1, j + 4);
+    for (int i = j + 1; i <= ie; ++i) {
+      double* Bij = Lb + bb_at(base, i, i - j, m);
+      for (int e = tid; e < m * m; e += blockDim.x) Ab[e / m][e % m] = Bij[e];
+      __syncthreads();
+      for (int e = tid; e < m * m; e += blockDim.x) {
+        const int r = e / m, cc = e % m;
+        double acc = 0;
+        for (int q = 0; q <= cc; ++q) acc += Ab[r][q] * Di[cc][q];
+        Bij[e] = acc;
+      }
+      __syncthreads();
+    }
+    // trailing update: B_ik -= L_ij L_kj^T for j < k <= i <= j + 4
+    for (int i = j + 1; i <= ie; ++i) {
+      const double* Lij = Lb + bb_at(base, i, i - j, m);
+      for (int e = tid; e < m * m; e += blockDim.x) Ab[e / m][e % m] = Lij[e];
+      __syncthreads();
+      for (int k = j + 1; k <= i; ++k) {
+        const double* Lkj = Lb + bb_at(base, k, k - j, m);
+        double* Bik = Lb + bb_at(base, i, i - k, m);
+        for (int e = tid; e < m * m; e += blockDim.x) {
+          const int r = e / m, cc = e % m;
+          double acc = 0;
+          for (int q = 0; q < m; ++q) acc += Ab[r][q] * Lkj[(long long)cc * m + q];
+          Bik[e] -= acc;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// x = S^-1 b on the coarsest level by block forward / backward substitution;
+// one block of threads per instance (its rows in the work table).
+template <typename TV>
+__global__ void __launch_bounds__(kBlock) k_bb_solve(const int* __restrict__ inst_list, const LInst* __restrict__ li,
+                                                     const TV* __restrict__ Lb, const TV* __restrict__ bvec,
+                                                     TV* __restrict__ xvec) {
+  const LInst& L = li[inst_list[blockIdx.x]];
+  const int T = L.n[0], m = L.N / T;
+  const long long base = L.doff;
+  __shared__ double ys[kBBMax * kBBMax];  // y then x (T * m <= 4096)
+  __shared__ double acc[kBBMax];
+  __shared__ double part[kBlock];
+  const int tid = threadIdx.x;
+  const int lanes = kBlock / m;             // threads per row (m <= 64, so >= 4)
+  const int r = tid / lanes, sub = tid % lanes;
+  const TV* B = bvec + L.voff;
+  TV* X = xvec + L.voff;
+  // forward: y_t = Dinv_t (b_t - sum_k L[t][k] y_{t-k})
+  for (int t = 0; t < T; ++t) {
+    double s = 0;
+    if (r < m) {
+      if (sub == 0) s = (double)B[(long long)t * m + r];
+      for (int k = 1; k <= 4 && k <= t; ++k) {
+        const TV* Lk = Lb + bb_at(base, t, k, m) + (long long)r * m;
+        const double* yk = ys + (t - k) * m;
+        for (int cc = sub; cc < m; cc += lanes) s -= (double)Lk[cc] * (double)yk[cc];
+      }
+    }
+    part[tid] = s;
+    __syncthreads();
+    if (r < m && sub == 0) {
+      double a = 0;
+      for (int q = 0; q < lanes; ++q) a += part[r * lanes + q];
+      acc[r] = a;
+    }
+    __syncthreads();
+    if (r < m) {
+      const TV* Di = Lb + bb_at(base, t, 0, m) + (long long)r * m;
+      double v = 0;
+      for (int cc = sub; cc <= r; cc += lanes) v += (double)Di[cc] * acc[cc];
+      part[tid] = v;
+    } else {
+      part[tid] = 0;
+    }
+    __syncthreads();
+    if (r < m && sub == 0) {
+      double a = 0;
+      for (int q = 0; q < lanes; ++q) a += part[r * lanes + q];
+      ys[t * m + r] = a;
+    }
+    __syncthreads();
+  }
+  // backward: x_t = Dinv_t^T (y_t - sum_k L[t+k][k]^T x_{t+k})
+  for (int t = T - 1; t >= 0; --t) {
+    double s = 0;
+    if (r < m) {
+      if (sub == 0) s = (double)ys[t * m + r];
+      for (int k = 1; k <= 4 && t + k < T; ++k) {
+        const TV* Lk = Lb + bb_at(base, t + k, k, m);
+        const double* xk = ys + (t + k) * m;
+        for (int q = sub; q < m; q += lanes) s -= (double)Lk[(long long)q * m + r] * (double)xk[q];
+      }
+    }
+    part[tid] = s;
+    __syncthreads();
+    if (r < m && sub == 0) {
+      double a = 0;
+      for (int q = 0; q < lanes; ++q) a += part[r * lanes + q];
+      acc[r] = a;
+    }
+    __syncthreads();
+    if (r < m) {
+      const TV* Di = Lb + bb_at(base, t, 0, m);
+      double v = 0;
+      for (int q = r + sub; q < m; q += lanes) v += (double)Di[(long long)q * m + r] * acc[q];
+      part[tid] = v;
+    } else {
+      part[tid] = 0;
+    }
+    __syncthreads();
+    if (r < m && sub == 0) {
+      double a = 0;
+      for (int q = 0; q < lanes; ++q) a += part[r * lanes + q];
+      ys[t * m + r] = a;
+      X[(long long)t * m + r] = (TV)a;
+    }
+    __syncthreads();
+  }
+}
+
 // In-place Gauss-Jordan inverse of one SPD matrix per block (FP64, no
 // pivoting: the coarsest operator is symmetric positive definite).
 __global__ void __launch_bounds__(1024) k_gauss_jordan(double* __restrict__ A, const long long* __restrict__ off,
@@ -607,6 +851,70 @@ __global__ void __launch_bounds__(1024) k_gauss_jordan(double* __restrict__ A, c
       }
     }
     __syncthreads();
+  }
+}
+
+// Banded Cholesky in place (FP64), one block per matrix.  A is column-major
+// N x N, symmetric positive definite, with A[i][j] = 0 for |i - j| > band
+// (the coarsest operator couples points at most 4 time steps apart, so in
+// time-major order the half-band is 5 * plane - 1).  The lower factor L
+// overwrites the lower band of A.
+__global__ void __launch_bounds__(kBlock) k_band_chol(double* __restrict__ A, const long long* __restrict__ off,
+                                                      const int* __restrict__ nn, const int* __restrict__ bw,
+                                                      int* __restrict__ fail) {
+  double* M = A + off[blockIdx.x];
+  const int n = nn[blockIdx.x], b = bw[blockIdx.x];
+  __shared__ double dk;
+  for (int k = 0; k < n; ++k) {
+    if (threadIdx.x == 0) {
+      const double a = M[(long long)k * n + k];
+      if (!(a > 0)) fail[blockIdx.x] = 1;
+      dk = a > 0 ? sqrt(a) : 1.0;
+      M[(long long)k * n + k] = dk;
+    }
+    __syncthreads();
+    const int hi = min(n - 1, k + b);
+    const double inv = 1.0 / dk;
+    for (int i = k + 1 + threadIdx.x; i <= hi; i += blockDim.x) M[(long long)k * n + i] *= inv;
+    __syncthreads();
+    // trailing update of the band: A[i][j] -= L[i][k] L[j][k], k < j <= i <= hi
+    const int m = hi - k;
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+      const int ii = e / m, jj = e - ii * m;
+      if (jj > ii) continue;
+      const int i = k + 1 + ii, j = k + 1 + jj;
+      M[(long long)j * n + i] -= M[(long long)k * n + i] * M[(long long)k * n + j];
+    }
+    __syncthreads();
+  }
+}
+
+// Dense inverse from a banded Cholesky factor: thread c solves L L^T x = e_c
+// and writes x as row c of X (X symmetric, so this is also column c); rows
+// are interleaved so that consecutive threads write consecutive addresses.
+__global__ void __launch_bounds__(kBlock) k_band_inverse(const double* __restrict__ Lf, double* __restrict__ X,
+                                                         const long long* __restrict__ off,
+                                                         const int* __restrict__ nn, const int* __restrict__ bw,
+                                                         const int* __restrict__ mat_of_block,
+                                                         const int* __restrict__ col0_of_block) {
+  const int mtx = mat_of_block[blockIdx.x];
+  const int n = nn[mtx], b = bw[mtx];
+  const int c = col0_of_block[blockIdx.x] + threadIdx.x;
+  if (c >= n) return;
+  const double* L = Lf + off[mtx];
+  double* Y = X + off[mtx];                 // Y[i * n + c] holds y_i then x_i
+  for (int i = 0; i < n; ++i) {             // forward: L y = e_c
+    double acc = (i == c) ? 1.0 : 0.0;
+    const int j0 = max(0, i - b);
+    if (i >= c)
+      for (int j = max(j0, c); j < i; ++j) acc -= L[(long long)j * n + i] * Y[(long long)j * n + c];
+    Y[(long long)i * n + c] = (i >= c) ? acc / L[(long long)i * n + i] : 0.0;
+  }
+  for (int i = n - 1; i >= 0; --i) {        // backward: L^T x = y
+    double acc = Y[(long long)i * n + c];
+    const int j1 = min(n - 1, i + b);
+    for (int j = i + 1; j <= j1; ++j) acc -= L[(long long)i * n + j] * Y[(long long)j * n + c];
+    Y[(long long)i * n + c] = acc / L[(long long)i * n + i];
   }
 }
 
@@ -1062,6 +1370,53 @@ void launch_set_unit(hipStream_t st, const LInst* probe, const int* col, int npr
 void launch_gauss_jordan(hipStream_t st, int nmat, double* A, const long long* off, const int* n, int* fail) {
   if (nmat <= 0) return;
   hipLaunchKernelGGL(k_gauss_jordan, dim3(nmat), dim3(1024), 0, st, A, off, n, fail);
+}
+
+void launch_set_probe(hipStream_t st, const LInst* probe, const int* pc, const int* ps, int nprobe, int ncolor,
+                      double* U) {
+  if (nprobe <= 0) return;
+  hipLaunchKernelGGL(k_set_probe, dim3(nprobe), dim3(64), 0, st, probe, pc, ps, nprobe, ncolor, U);
+}
+
+void launch_extract_probe(hipStream_t st, const Work* w, int nb, const LInst* probe, const int* pc, const int* ps,
+                          const long long* dout, int ncolor, const double* Y, double* S) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(k_extract_probe, dim3(nb), dim3(kBlock), 0, st, w, probe, pc, ps, dout, ncolor, Y, S);
+}
+
+void launch_extract_band(hipStream_t st, const Work* w, int nb, const LInst* probe, const int* pc, const int* ps,
+                         const long long* bout, int ncolor, const double* Y, double* Lb) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(k_extract_band, dim3(nb), dim3(kBlock), 0, st, w, probe, pc, ps, bout, ncolor, Y, Lb);
+}
+
+void launch_bb_factor(hipStream_t st, int nmat, double* Lb, const long long* boff, const int* T, const int* m,
+                      int* fail) {
+  if (nmat <= 0) return;
+  hipLaunchKernelGGL(k_bb_factor, dim3(nmat), dim3(kBlock), 0, st, Lb, boff, T, m, fail);
+}
+
+template <typename TV>
+void launch_bb_solve(hipStream_t st, int ninst, const int* inst_list, const LInst* li, const TV* Lb, const TV* b,
+                     TV* x) {
+  if (ninst <= 0) return;
+  hipLaunchKernelGGL((k_bb_solve<TV>), dim3(ninst), dim3(kBlock), 0, st, inst_list, li, Lb, b, x);
+}
+template void launch_bb_solve<float>(hipStream_t, int, const int*, const LInst*, const float*, const float*, float*);
+template void launch_bb_solve<double>(hipStream_t, int, const int*, const LInst*, const double*, const double*,
+                                      double*);
+
+void launch_band_chol(hipStream_t st, int nmat, double* A, const long long* off, const int* n, const int* bw,
+                      int* fail) {
+  if (nmat <= 0) return;
+  hipLaunchKernelGGL(k_band_chol, dim3(nmat), dim3(kBlock), 0, st, A, off, n, bw, fail);
+}
+
+void launch_band_inverse(hipStream_t st, int nblocks, const double* L, double* X, const long long* off,
+                         const int* n, const int* bw, const int* mat_of_block, const int* col0_of_block) {
+  if (nblocks <= 0) return;
+  hipLaunchKernelGGL(k_band_inverse, dim3(nblocks), dim3(kBlock), 0, st, L, X, off, n, bw, mat_of_block,
+                     col0_of_block);
 }
 
 template <typename TV>

@@ -29,6 +29,21 @@ void launch_coarsen_coef(int D, hipStream_t st, const Work* w, int nb, const LIn
                          const TC* cf, TC* cc);
 void launch_set_unit(hipStream_t st, const LInst* probe, const int* col, int nprobe, double* U);
 void launch_gauss_jordan(hipStream_t st, int nmat, double* A, const long long* off, const int* n, int* fail);
+void launch_set_probe(hipStream_t st, const LInst* probe, const int* pc, const int* ps, int nprobe, int ncolor,
+                      double* U);
+void launch_extract_probe(hipStream_t st, const Work* w, int nb, const LInst* probe, const int* pc, const int* ps,
+                          const long long* dout, int ncolor, const double* Y, double* S);
+void launch_extract_band(hipStream_t st, const Work* w, int nb, const LInst* probe, const int* pc, const int* ps,
+                         const long long* bout, int ncolor, const double* Y, double* Lb);
+void launch_bb_factor(hipStream_t st, int nmat, double* Lb, const long long* boff, const int* T, const int* m,
+                      int* fail);
+template <typename TV>
+void launch_bb_solve(hipStream_t st, int ninst, const int* inst_list, const LInst* li, const TV* Lb, const TV* b,
+                     TV* x);
+void launch_band_chol(hipStream_t st, int nmat, double* A, const long long* off, const int* n, const int* bw,
+                      int* fail);
+void launch_band_inverse(hipStream_t st, int nblocks, const double* L, double* X, const long long* off,
+                         const int* n, const int* bw, const int* mat_of_block, const int* col0_of_block);
 template <typename TV>
 void launch_convert_dense(hipStream_t st, const double* src, TV* dst, long long n);
 template <typename TV>

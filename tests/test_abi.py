@@ -29,7 +29,7 @@ def test_default_options():
     lib = N.load()
     o = N.Options()
     assert lib.mpde_default_options(ctypes.byref(o)) == 0
-    assert o.tol == 1e-6 and o.nu == 2 and o.max_inner == 200 and o.coarse_min == 4
+    assert o.tol == 1e-6 and o.nu == 2 and o.max_inner == 200 and o.coarse_min == 8
     assert lib.mpde_default_options(None) == N.MPDE_ERR_INVALID_ARG
 
 

@@ -92,10 +92,14 @@ def test_minimum_grid_no_coarsening():
 def test_level_plan():
     inst = W.reaction_diffusion_2d(0, shape=(32, 64, 64))
     prob, zs, info = gpu_solve([inst], "f32")
-    assert prob.levels(0) == [(32, 64, 64), (32, 32, 32), (32, 16, 16), (32, 8, 8), (32, 4, 4)]
+    assert prob.levels(0) == [(32, 64, 64), (32, 32, 32), (32, 16, 16), (32, 8, 8)]
     inst = W.reaction_diffusion_1d_ragged(0, (24, 48))
     prob, zs, info = gpu_solve([inst], "f32")
     assert prob.levels(0) == [(24, 48), (24, 24), (24, 12), (24, 6)]
+    # a long time axis: periodic axes continue to 4 so the coarsest grid fits
+    inst = W.reaction_diffusion_2d(0, shape=(64, 32, 32))
+    prob, zs, info = gpu_solve([inst], "f32")
+    assert prob.levels(0) == [(64, 32, 32), (64, 16, 16), (64, 8, 8), (64, 4, 4)]
 
 
 def test_nonfinite_input_rejected():
