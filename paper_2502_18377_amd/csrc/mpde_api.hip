@@ -110,8 +110,8 @@ struct Level {
   LInst* d = nullptr;
   long long npts = 0;          // total points of this level
   Table all, smooth, dense;    // all instances / non-coarsest / coarsest (rows)
-  std::vector<int> cinst;      // instances whose coarsest level is this one
-  int* d_cinst = nullptr;
+  std::vector<int> cinst64, cinstg;   // coarsest here: 64-point planes / other planes
+  int *d_cinst64 = nullptr, *d_cinstg = nullptr;
   void* coef = nullptr;        // TC [K planes per instance]
   void *x = nullptr, *r = nullptr, *dd = nullptr, *b = nullptr, *gam = nullptr, *dinv = nullptr;
 };
@@ -277,7 +277,9 @@ struct Solver {
   void vcycle(int l, TV* b, TV* x) {
     Level& L = P->lv[l];
     const int nu = P->opt.nu;
-    if (!L.cinst.empty()) launch_bb_solve<TV>(st, (int)L.cinst.size(), L.d_cinst, L.d, V(P->Sinv), b, x);
+    if (!L.cinst64.empty())
+      launch_bb_solve64<TV>(st, (int)L.cinst64.size(), L.d_cinst64, L.d, V(P->Sinv), b, x);
+    if (!L.cinstg.empty()) launch_bb_solve<TV>(st, (int)L.cinstg.size(), L.d_cinstg, L.d, V(P->Sinv), b, x);
     if (L.smooth.nb() == 0) return;
     const Table& t = L.smooth;
     launch_cheb_init<TV>(st, t.d, t.nb(), L.d, b, V(L.dinv), x, V(L.r), V(L.dd));
@@ -521,13 +523,22 @@ struct Solver {
                                    " is not positive definite (rank-deficient problem?)");
     for (int l = 0; l < (int)P->lv.size(); ++l) {
       Level& L = P->lv[l];
-      L.cinst.clear();
+      L.cinst64.clear();
+      L.cinstg.clear();
       for (int b = 0; b < B; ++b)
-        if (L.h[b].N && L.h[b].coarsest) { L.h[b].doff = boff[b]; L.cinst.push_back(b); }
-      if (!L.cinst.empty()) {
+        if (L.h[b].N && L.h[b].coarsest) {
+          L.h[b].doff = boff[b];
+          (mn[b] == 64 ? L.cinst64 : L.cinstg).push_back(b);
+        }
+      if (!L.cinst64.empty() || !L.cinstg.empty())
         HIPCHK(hipMemcpyAsync(L.d, L.h.data(), L.h.size() * sizeof(LInst), hipMemcpyHostToDevice, st));
-        L.d_cinst = P->alloc<int>(L.cinst.size());
-        HIPCHK(hipMemcpyAsync(L.d_cinst, L.cinst.data(), L.cinst.size() * sizeof(int), hipMemcpyHostToDevice, st));
+      if (!L.cinst64.empty()) {
+        L.d_cinst64 = P->alloc<int>(L.cinst64.size());
+        HIPCHK(hipMemcpyAsync(L.d_cinst64, L.cinst64.data(), L.cinst64.size() * sizeof(int), hipMemcpyHostToDevice, st));
+      }
+      if (!L.cinstg.empty()) {
+        L.d_cinstg = P->alloc<int>(L.cinstg.size());
+        HIPCHK(hipMemcpyAsync(L.d_cinstg, L.cinstg.data(), L.cinstg.size() * sizeof(int), hipMemcpyHostToDevice, st));
       }
     }
     HIPCHK(hipStreamSynchronize(st));

@@ -709,22 +709,25 @@ __global__ void __launch_bounds__(kBlock) k_bb_factor(double* __restrict__ Lb, c
       }
       __syncthreads();
     }
-    // trailing update: B_ik -= L_ij L_kj^T for j < k <= i <= j + 4
-    for (int i = j + 1; i <= ie; ++i) {
-      const double* Lij = Lb + bb_at(base, i, i - j, m);
-      for (int e = tid; e < m * m; e += blockDim.x) Ab[e / m][e % m] = Lij[e];
+    // trailing update: B_ik -= L_ij L_kj^T for j < k <= i <= j + 4, with
+    // L_kj staged in LDS (Di is free once the off-diagonal blocks are done)
+    for (int k = j + 1; k <= ie; ++k) {
+      const double* Lkj = Lb + bb_at(base, k, k - j, m);
+      for (int e = tid; e < m * m; e += blockDim.x) Di[e / m][e % m] = Lkj[e];
       __syncthreads();
-      for (int k = j + 1; k <= i; ++k) {
-        const double* Lkj = Lb + bb_at(base, k, k - j, m);
+      for (int i = k; i <= ie; ++i) {
+        const double* Lij = Lb + bb_at(base, i, i - j, m);
+        for (int e = tid; e < m * m; e += blockDim.x) Ab[e / m][e % m] = Lij[e];
+        __syncthreads();
         double* Bik = Lb + bb_at(base, i, i - k, m);
         for (int e = tid; e < m * m; e += blockDim.x) {
           const int r = e / m, cc = e % m;
           double acc = 0;
-          for (int q = 0; q < m; ++q) acc += Ab[r][q] * Lkj[(long long)cc * m + q];
+          for (int q = 0; q < m; ++q) acc += Ab[r][q] * Di[cc][q];
           Bik[e] -= acc;
         }
+        __syncthreads();
       }
-      __syncthreads();
     }
   }
 }
@@ -1396,13 +1399,125 @@ void launch_bb_factor(hipStream_t st, int nmat, double* Lb, const long long* bof
   hipLaunchKernelGGL(k_bb_factor, dim3(nmat), dim3(kBlock), 0, st, Lb, boff, T, m, fail);
 }
 
+// Specialisation for 64-point planes: thread (r, h) owns 16 consecutive
+// columns h*16..h*16+15 of row r in every block; the four off-diagonal
+// blocks of the next step are prefetched into registers while the current
+// step's reductions run.
+template <typename TV>
+__global__ void __launch_bounds__(kBlock) k_bb_solve64(const int* __restrict__ inst_list,
+                                                       const LInst* __restrict__ li, const TV* __restrict__ Lb,
+                                                       const TV* __restrict__ bvec, TV* __restrict__ xvec) {
+  constexpr int M = 64, CW = 16;
+  const LInst& L = li[inst_list[blockIdx.x]];
+  const int T = L.n[0];
+  const long long base = L.doff;
+  __shared__ double ys[4096];
+  __shared__ double acc[M];
+  const int tid = threadIdx.x, r = tid >> 2, h = tid & 3, c0 = h * CW;
+  const TV* B = bvec + L.voff;
+  TV* X = xvec + L.voff;
+  TV pre[4][CW];
+  auto load_fwd = [&](int t) {
+#pragma unroll
+    for (int k = 1; k <= 4; ++k) {
+      if (t - k >= 0 && t < T) {
+        const TV* Lk = Lb + bb_at(base, t, k, M) + r * M + c0;
+#pragma unroll
+        for (int q = 0; q < CW; ++q) pre[k - 1][q] = Lk[q];
+      }
+    }
+  };
+  load_fwd(0);
+  for (int t = 0; t < T; ++t) {
+    double s = (h == 0) ? (double)B[(long long)t * M + r] : 0.0;
+#pragma unroll
+    for (int k = 1; k <= 4; ++k)
+      if (t - k >= 0) {
+        const double* yk = ys + (t - k) * M + c0;
+#pragma unroll
+        for (int q = 0; q < CW; ++q) s -= (double)pre[k - 1][q] * yk[q];
+      }
+    TV dr[CW];
+    {
+      const TV* Di = Lb + bb_at(base, t, 0, M) + r * M + c0;
+#pragma unroll
+      for (int q = 0; q < CW; ++q) dr[q] = Di[q];
+    }
+    load_fwd(t + 1);
+    s += __shfl_xor(s, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    if (h == 0) acc[r] = s;
+    __syncthreads();
+    double v = 0;
+#pragma unroll
+    for (int q = 0; q < CW; ++q) v += (double)dr[q] * acc[c0 + q];   // Dinv lower: upper entries are 0
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    if (h == 0) ys[t * M + r] = v;
+    __syncthreads();
+  }
+  // backward: x_t = Dinv_t^T (y_t - sum_k L[t+k][k]^T x_{t+k}); thread (r, h)
+  // accumulates column r over rows h*16..h*16+15 of each block.
+  auto load_bwd = [&](int t) {
+#pragma unroll
+    for (int k = 1; k <= 4; ++k) {
+      if (t >= 0 && t + k < T) {
+        const TV* Lk = Lb + bb_at(base, t + k, k, M);
+#pragma unroll
+        for (int q = 0; q < CW; ++q) pre[k - 1][q] = Lk[(c0 + q) * M + r];
+      }
+    }
+  };
+  load_bwd(T - 1);
+  for (int t = T - 1; t >= 0; --t) {
+    double s = (h == 0) ? ys[t * M + r] : 0.0;
+#pragma unroll
+    for (int k = 1; k <= 4; ++k)
+      if (t + k < T) {
+        const double* xk = ys + (t + k) * M + c0;
+#pragma unroll
+        for (int q = 0; q < CW; ++q) s -= (double)pre[k - 1][q] * xk[q];
+      }
+    TV dc[CW];
+    {
+      const TV* Di = Lb + bb_at(base, t, 0, M);
+#pragma unroll
+      for (int q = 0; q < CW; ++q) dc[q] = Di[(c0 + q) * M + r];
+    }
+    load_bwd(t - 1);
+    s += __shfl_xor(s, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    if (h == 0) acc[r] = s;
+    __syncthreads();
+    double v = 0;
+#pragma unroll
+    for (int q = 0; q < CW; ++q) v += (double)dc[q] * acc[c0 + q];
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    __syncthreads();
+    if (h == 0) { ys[t * M + r] = v; X[(long long)t * M + r] = (TV)v; }
+    __syncthreads();
+  }
+}
+
 template <typename TV>
 void launch_bb_solve(hipStream_t st, int ninst, const int* inst_list, const LInst* li, const TV* Lb, const TV* b,
                      TV* x) {
   if (ninst <= 0) return;
   hipLaunchKernelGGL((k_bb_solve<TV>), dim3(ninst), dim3(kBlock), 0, st, inst_list, li, Lb, b, x);
 }
+
+template <typename TV>
+void launch_bb_solve64(hipStream_t st, int ninst, const int* inst_list, const LInst* li, const TV* Lb, const TV* b,
+                       TV* x) {
+  if (ninst <= 0) return;
+  hipLaunchKernelGGL((k_bb_solve64<TV>), dim3(ninst), dim3(kBlock), 0, st, inst_list, li, Lb, b, x);
+}
 template void launch_bb_solve<float>(hipStream_t, int, const int*, const LInst*, const float*, const float*, float*);
+template void launch_bb_solve64<float>(hipStream_t, int, const int*, const LInst*, const float*, const float*,
+                                       float*);
+template void launch_bb_solve64<double>(hipStream_t, int, const int*, const LInst*, const double*, const double*,
+                                        double*);
 template void launch_bb_solve<double>(hipStream_t, int, const int*, const LInst*, const double*, const double*,
                                       double*);
 
