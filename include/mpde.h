@@ -176,6 +176,68 @@ typedef struct {
 } mpde_kstat;
 int mpde_kernel_stats(const mpde_problem *p, mpde_kstat *out, int32_t max);
 
+/* ---------------------------------------------------------------------
+ * Learned coarse-grid correction (an addition to the paper's solver): a
+ * 3-layer 3x3x3 convolution network, 16 channels, BF16 weights with FP32
+ * accumulation, mapping the normalised restricted residual plus the
+ * coefficient fields of a grid level to the coarse-grid correction, used in
+ * place of the recursive V-cycle below that level inside flexible CG.  It
+ * is trained on systems built by mpde_build with the solver's own operator:
+ * the loss is the energy-norm error o^T S o - 2 o^T r of the prediction o for
+ * a unit residual r (minimised by o = S^-1 r).
+ * ------------------------------------------------------------------- */
+typedef struct mpde_net mpde_net;   /* opaque, library-owned weights + Adam state */
+
+/* Parameters of a network: 3 layers x (27*16*16 weights [tap][out][in] +
+ * 16 biases), FP32 master copy. */
+#define MPDE_NET_PARAMS (3 * (27 * 16 * 16 + 16))
+
+/* New network on the current device with seeded (He-scaled) weights; the
+ * last layer starts at zero (an untrained network is plain multigrid).  in_channels (2..16) = 2 + K: the normalised
+ * residual, the plain V-cycle's coarse correction (Jacobi units) and the K
+ * coefficient fields of the level.  The network refines the plain
+ * correction: e = V(r) + D^-1 N(r, V(r), c) ||r||, so N = 0 is plain MG. */
+int mpde_net_create(int32_t in_channels, uint64_t seed, mpde_net **out);
+
+/* One Adam step (learning rate lr) on residual samples drawn from problem p
+ * at grid level `level` (>= 1): a random right-hand side per instance is
+ * smoothed on the finer levels and restricted, exactly as in a V-cycle.
+ * *loss and *loss_plain (host, may be NULL) receive the mean normalised
+ * energy loss of the learned correction and of the plain V-cycle's on the
+ * same samples (lower is better; the exact coarse solve attains the minimum).
+ * Errors: INVALID_ARG (bad level / mismatched channels), UNSUPPORTED (FP64
+ * problem), HIP. */
+int mpde_net_train_step(mpde_net *net, mpde_problem *p, int32_t level, uint64_t seed, double lr, double *loss,
+                        double *loss_plain);
+
+/* Use net (borrowed; it must outlive its use) for the coarse correction of
+ * level `level` in later mpde_solve / mpde_solve_adjoint calls on p; the
+ * Krylov method becomes flexible CG.  net == NULL restores plain multigrid. */
+int mpde_net_attach(mpde_problem *p, const mpde_net *net, int32_t level);
+
+/* Copy the FP32 master parameters out of / into a network (host arrays of
+ * n >= MPDE_NET_PARAMS floats). */
+int mpde_net_get(const mpde_net *net, float *host, int64_t n);
+int mpde_net_set(mpde_net *net, const float *host, int64_t n);
+void mpde_net_free(mpde_net *net);
+
+/* One convolution layer (parity and training building block).  x_bf16:
+ * device [batch][T][X][Y][16] bf16; w_bf16: device [27][16][16] bf16 indexed
+ * [tap][out][in] for sign = +1 (forward) or [tap][in][out] (the transposed
+ * weights) with sign = -1 (data gradient: taps mirrored); bias: device [16]
+ * FP32 or NULL; outputs y (device FP32, same shape) and/or y_bf16 (bf16 of
+ * relu(y) if relu != 0, else of y); either may be NULL.  Taps are ordered
+ * (dt, dx, dy) in {-1,0,1}^3 with dt slowest; periodic[a] selects
+ * wrap-around, otherwise zero padding. */
+int mpde_conv3d(const void *x_bf16, const void *w_bf16, const float *bias, float *y, void *y_bf16,
+                int32_t relu, int32_t sign, int32_t batch, int32_t T, int32_t X, int32_t Y,
+                const int32_t *periodic, void *stream);
+
+/* Weight gradient of one layer: dw[27][16][16] (device FP32) =
+ * sum over points of dy[p][out] * x[p + off(tap)][in]. */
+int mpde_conv3d_wgrad(const void *x_bf16, const void *dy_bf16, float *dw, int32_t batch, int32_t T, int32_t X,
+                      int32_t Y, const int32_t *periodic, void *stream);
+
 /* Grid levels planned for instance b (0 if p is NULL or b out of range);
  * if shapes is not NULL it receives levels*D points-per-axis values. */
 int mpde_levels(const mpde_problem *p, int32_t b, int32_t *shapes);

@@ -13,7 +13,10 @@ MPDE_BC_NONE, MPDE_BC_DIRICHLET, MPDE_BC_PERIODIC = 0, 1, 2
 BC_CODES = {"none": MPDE_BC_NONE, "dirichlet": MPDE_BC_DIRICHLET, "periodic": MPDE_BC_PERIODIC}
 
 EXPORTS = ("mpde_default_options", "mpde_build", "mpde_solve", "mpde_solve_adjoint",
-           "mpde_free", "mpde_last_error", "mpde_levels", "mpde_kernel_stats")
+           "mpde_free", "mpde_last_error", "mpde_levels", "mpde_kernel_stats",
+           "mpde_net_create", "mpde_net_train_step", "mpde_net_attach", "mpde_net_get", "mpde_net_set",
+           "mpde_net_free", "mpde_conv3d", "mpde_conv3d_wgrad")
+NET_PARAMS = 3 * (27 * 16 * 16 + 16)
 
 
 class Options(ctypes.Structure):
@@ -78,6 +81,19 @@ def load():
     lib.mpde_levels.restype = ctypes.c_int
     lib.mpde_kernel_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(KStat), ctypes.c_int32]
     lib.mpde_kernel_stats.restype = ctypes.c_int
+    vp, i32, i64, u64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+    lib.mpde_net_create.argtypes = [i32, u64, ctypes.POINTER(vp)]
+    lib.mpde_net_train_step.argtypes = [vp, vp, i32, u64, dbl, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
+    lib.mpde_net_attach.argtypes = [vp, vp, i32]
+    lib.mpde_net_get.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i64]
+    lib.mpde_net_set.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i64]
+    lib.mpde_net_free.argtypes = [vp]
+    lib.mpde_net_free.restype = None
+    lib.mpde_conv3d.argtypes = [vp, vp, vp, vp, vp, i32, i32, i32, i32, i32, i32, ctypes.POINTER(i32), vp]
+    lib.mpde_conv3d_wgrad.argtypes = [vp, vp, vp, i32, i32, i32, i32, ctypes.POINTER(i32), vp]
+    for f in ("mpde_net_create", "mpde_net_train_step", "mpde_net_attach", "mpde_net_get", "mpde_net_set",
+              "mpde_conv3d", "mpde_conv3d_wgrad"):
+        getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
 

@@ -34,6 +34,7 @@
 #include "../../include/mpde.h"
 #include "mpde_internal.hpp"
 #include "mpde_kernels.hpp"
+#include "mpde_conv.hpp"
 
 using namespace mpde;
 
@@ -118,6 +119,37 @@ struct Level {
 
 }  // namespace
 
+// Learned coarse correction: FP32 master parameters, Adam state and bf16
+// weight copies (layout [tap][out][in] and transposed [tap][in][out]).
+struct mpde_net {
+  int cin = 1;
+  long long t = 0;                   // Adam step
+  float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+  unsigned short *wb = nullptr, *wtb = nullptr;   // 3 layers x 27*256
+  float* partial = nullptr;          // weight-gradient block partials
+  std::vector<void*> owned;
+  ~mpde_net() {
+    for (void* p : owned) (void)hipFree(p);
+  }
+};
+
+namespace {
+constexpr int kLayerW = 27 * 256;
+constexpr int kLayerP = kLayerW + 16;
+}  // namespace
+
+// Per-problem buffers of the network at its grid level.
+struct NetScratch {
+  int level = -1;
+  long long npts = 0;
+  int ntiles = 0;
+  mpde::Grid3* grids = nullptr;
+  int2* tiles = nullptr;
+  unsigned short *X0 = nullptr, *A1 = nullptr, *A2 = nullptr, *Db = nullptr;
+  float *P1 = nullptr, *P2 = nullptr, *Y3 = nullptr, *dA = nullptr, *dB = nullptr;
+  double *norm = nullptr, *inv = nullptr;
+};
+
 struct mpde_problem {
   int dtype = 0, D = 0, B = 0, K = 0, V = 0;
   uint32_t mset = 0;
@@ -139,6 +171,12 @@ struct mpde_problem {
   int *active = nullptr, *iters = nullptr, *flag = nullptr;
   void* Sinv = nullptr;                                    // TV dense inverses
   bool has_solution = false;
+  const mpde_net* net = nullptr;                           // learned coarse correction
+  int net_level = 0;
+  NetScratch ns;
+  void* zp = nullptr;                                      // previous z (flexible CG)
+  double* rzp = nullptr;
+  long long fallbacks = 0;                                 // learned -> plain V-cycle switches
   // profiling (options.profile): event pairs around finest-grid kernels
   struct Rec { int kind; hipEvent_t a, b; double bytes; };
   std::vector<Rec> recs;
@@ -200,7 +238,163 @@ struct Solver {
   mpde_problem* P;
   hipStream_t st;
   int D;
+  bool use_net = true;
   explicit Solver(mpde_problem* p) : P(p), st(p->st), D(p->D) {}
+
+  // ---------------------------------------------------------- network
+  // Scratch and conv tables for the network at level l (all instances that
+  // have level l).
+  void net_setup(int l) {
+    NetScratch& S = P->ns;
+    if (S.level == l) return;
+    Level& L = P->lv[l];
+    std::vector<mpde::Grid3> g(P->B);
+    std::vector<int2> tiles;
+    for (int b = 0; b < P->B; ++b) {
+      const LInst& q = L.h[b];
+      g[b] = mpde::Grid3{q.n[0], q.n[1], D == 3 ? q.n[2] : 1, {q.per[0], q.per[1], D == 3 ? q.per[2] : 0}, q.voff};
+      for (int s0 = 0; s0 < q.N; s0 += 16) tiles.push_back(make_int2(b, s0));
+    }
+    while (tiles.size() % 4) tiles.push_back(make_int2(-1, 0));
+    S.level = l;
+    S.npts = L.npts;
+    S.ntiles = (int)tiles.size();
+    S.grids = P->alloc<mpde::Grid3>(P->B);
+    S.tiles = P->alloc<int2>(tiles.size());
+    HIPCHK(hipMemcpy(S.grids, g.data(), P->B * sizeof(mpde::Grid3), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(S.tiles, tiles.data(), tiles.size() * sizeof(int2), hipMemcpyHostToDevice));
+    const size_t n16 = (size_t)L.npts * 16;
+    S.X0 = P->alloc<unsigned short>(n16);
+    S.A1 = P->alloc<unsigned short>(n16);
+    S.A2 = P->alloc<unsigned short>(n16);
+    S.Db = P->alloc<unsigned short>(n16);
+    S.P1 = P->alloc<float>(n16);
+    S.P2 = P->alloc<float>(n16);
+    S.Y3 = P->alloc<float>(n16);
+    S.dA = P->alloc<float>(n16);
+    S.dB = P->alloc<float>(n16);
+    S.norm = P->alloc<double>(P->B);
+    S.inv = P->alloc<double>(P->B);
+  }
+
+  // Per-instance ||r|| and 1/||r|| of a level vector into ns.norm / ns.inv.
+  void level_norms(int l, const TV* r) {
+    Level& L = P->lv[l];
+    launch_dot<double, TV>(st, L.all.d, L.all.nb(), L.d, r, r, P->partial);
+    finish(L.all, P->pq);
+    std::vector<double> n2(P->B), nn(P->B), iv(P->B);
+    HIPCHK(hipMemcpyAsync(n2.data(), P->pq, P->B * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int b = 0; b < P->B; ++b) {
+      nn[b] = std::sqrt(std::max(n2[b], 0.0));
+      iv[b] = nn[b] > 0 ? 1.0 / nn[b] : 0.0;
+    }
+    HIPCHK(hipMemcpyAsync(P->ns.norm, nn.data(), P->B * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(P->ns.inv, iv.data(), P->B * sizeof(double), hipMemcpyHostToDevice, st));
+  }
+
+  void net_forward(const mpde_net* net) {
+    NetScratch& S = P->ns;
+    const unsigned short* W = net->wb;
+    const float* bias = net->w;
+    conv_launch(st, S.ntiles, S.tiles, S.grids, S.X0, W, bias + kLayerW, 1, S.P1, S.A1, 1);
+    conv_launch(st, S.ntiles, S.tiles, S.grids, S.A1, W + kLayerW, bias + kLayerP + kLayerW, 1, S.P2, S.A2, 1);
+    conv_launch(st, S.ntiles, S.tiles, S.grids, S.A2, W + 2 * kLayerW, bias + 2 * kLayerP + kLayerW, 1, S.Y3,
+                nullptr, 0);
+  }
+
+  // Learned coarse correction on level l: the plain V-cycle's correction
+  // v = V_l(b) plus the network's refinement, x = v + D^-1 N(b, v, c) ||b||.
+  void learned(int l, TV* b, TV* x) {
+    Level& L = P->lv[l];
+    const bool keep = use_net;
+    use_net = false;
+    vcycle(l, b, x);
+    use_net = keep;
+    level_norms(l, b);
+    features_launch(st, L.all.d, L.all.nb(), L.d, P->K, (const float*)b, (const float*)x, (const float*)L.dinv,
+                    P->ns.inv, (const float*)L.coef, P->ns.X0);
+    net_forward(P->net);
+    net_out_launch(st, L.all.d, L.all.nb(), L.d, P->ns.Y3, (const float*)L.dinv, P->ns.norm, (float*)x);
+  }
+
+  // Training residuals at level l: a hashed right-hand side per instance on
+  // the finest grid, Chebyshev-smoothed and restricted level by level as in
+  // the down leg of a V-cycle; the result is left in lv[l].b.
+  void sample_residuals(int l, unsigned seed) {
+    for (int k = 0; k < l; ++k) {
+      Level& L = P->lv[k];
+      const Table& t = L.smooth;
+      if (k == 0) launch_hash_fill<TV>(st, t.d, t.nb(), L.d, V(L.b), seed);
+      launch_cheb_init<TV>(st, t.d, t.nb(), L.d, V(L.b), V(L.dinv), V(L.x), V(L.r), V(L.dd));
+      chebyshev(k, V(L.x), P->opt.nu);
+      Level& Cc = P->lv[k + 1];
+      launch_restrict<TV>(D, st, Cc.all.d, Cc.all.nb(), L.d, Cc.d, V(L.r), V(Cc.b));
+    }
+  }
+
+  // One training step of net on problem level l; returns the mean energy
+  // loss of the learned correction and (loss_plain) of the plain V-cycle's.
+  double train_step(mpde_net* net, int l, unsigned seed, double lr, double* loss_plain) {
+    net_setup(l);
+    NetScratch& S = P->ns;
+    Level& L = P->lv[l];
+    sample_residuals(l, seed);
+    // plain coarse correction v = V_l(r) into a scratch level vector
+    TV* v = (TV*)S.dB;                      // FP32 scratch, >= L.npts entries
+    const bool keep = use_net;
+    use_net = false;
+    vcycle(l, V(L.b), v);
+    use_net = keep;
+    level_norms(l, V(L.b));
+    int nb_inst = 0;
+    for (int b = 0; b < P->B; ++b) nb_inst += L.h[b].N > 0;
+    // reference: energy loss of the plain correction
+    scale_vec_launch(st, L.all.d, L.all.nb(), L.d, (const float*)v, S.inv, (float*)L.dd);
+    apply(l, L.all, V(L.dd), V(L.r), G_STORE, nullptr);
+    energy_grad_launch(st, L.all.d, L.all.nb(), L.d, (const float*)L.dd, (const float*)L.r, (const float*)L.b,
+                       S.inv, (const float*)L.dinv, 1.0f, nullptr, P->partial);
+    finish(L.all, P->rzp);
+    // learned correction
+    features_launch(st, L.all.d, L.all.nb(), L.d, P->K, (const float*)L.b, (const float*)v, (const float*)L.dinv,
+                    S.inv, (const float*)L.coef, S.X0);
+    net_forward(net);
+    predict_launch(st, L.all.d, L.all.nb(), L.d, S.Y3, (const float*)v, (const float*)L.dinv, S.inv, (float*)L.dd);
+    apply(l, L.all, V(L.dd), V(L.r), G_STORE, nullptr);
+    energy_grad_launch(st, L.all.d, L.all.nb(), L.d, (const float*)L.dd, (const float*)L.r, (const float*)L.b,
+                       S.inv, (const float*)L.dinv, 1.0f / nb_inst, S.dA, P->partial);
+    finish(L.all, P->rz);
+    std::vector<double> lossb(P->B), lossp(P->B);
+    HIPCHK(hipMemcpyAsync(lossb.data(), P->rz, P->B * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(lossp.data(), P->rzp, P->B * sizeof(double), hipMemcpyDeviceToHost, st));
+    // backward through the three layers
+    const long long n16 = S.npts * 16;
+    float* gw = net->g;
+    const unsigned short* Wt = net->wtb;
+    to_bf16_launch(st, S.dA, n16, S.Db);                                              // dY3
+    conv_wgrad_launch(st, S.ntiles, S.tiles, S.grids, S.A2, S.Db, net->partial, gw + 2 * kLayerP);
+    bias_grad_launch(st, S.dA, S.npts, gw + 2 * kLayerP + kLayerW);
+    conv_launch(st, S.ntiles, S.tiles, S.grids, S.Db, Wt + 2 * kLayerW, nullptr, -1, S.dB, nullptr, 0);
+    relu_bwd_launch(st, S.dB, S.P2, n16, S.dA, S.Db);                                 // dpre2
+    conv_wgrad_launch(st, S.ntiles, S.tiles, S.grids, S.A1, S.Db, net->partial, gw + kLayerP);
+    bias_grad_launch(st, S.dA, S.npts, gw + kLayerP + kLayerW);
+    conv_launch(st, S.ntiles, S.tiles, S.grids, S.Db, Wt + kLayerW, nullptr, -1, S.dB, nullptr, 0);
+    relu_bwd_launch(st, S.dB, S.P1, n16, S.dA, S.Db);                                 // dpre1
+    conv_wgrad_launch(st, S.ntiles, S.tiles, S.grids, S.X0, S.Db, net->partial, gw);
+    bias_grad_launch(st, S.dA, S.npts, gw + kLayerW);
+    net->t += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    adam_launch(st, net->w, gw, net->m, net->v, 3 * kLayerP, (float)lr, b1, b2, 1e-8f,
+                1.f - std::pow(b1, (float)net->t), 1.f - std::pow(b2, (float)net->t));
+    for (int k = 0; k < 3; ++k)
+      pack_weights_launch(st, net->w + k * kLayerP, net->wb + k * kLayerW, net->wtb + k * kLayerW);
+    HIPCHK(hipStreamSynchronize(st));
+    double tot = 0, totp = 0;
+    for (int b = 0; b < P->B; ++b)
+      if (L.h[b].N > 0) { tot += lossb[b]; totp += lossp[b]; }
+    if (loss_plain) *loss_plain = totp / std::max(1, nb_inst);
+    return tot / std::max(1, nb_inst);
+  }
 
   TV* V(void* p) { return (TV*)p; }
   TC* C(void* p) { return (TC*)p; }
@@ -286,7 +480,8 @@ struct Solver {
     chebyshev(l, x, nu);
     Level& Cc = P->lv[l + 1];
     launch_restrict<TV>(D, st, Cc.all.d, Cc.all.nb(), L.d, Cc.d, V(L.r), V(Cc.b));
-    vcycle(l + 1, V(Cc.b), V(Cc.x));
+    if (use_net && P->net && l + 1 == P->net_level) learned(l + 1, V(Cc.b), V(Cc.x));
+    else vcycle(l + 1, V(Cc.b), V(Cc.x));
     launch_prolong_add<TV>(D, st, t.d, t.nb(), L.d, Cc.d, V(Cc.x), x);
     pbeg(l);
     launch_gamma<TV, TV, TC>(D, st, t.d, t.nb(), L.d, P->ci, x, C(L.coef), C(P->f), 0, V(L.gam));
@@ -305,14 +500,44 @@ struct Solver {
     const int B = P->B;
     launch_fill<TV>(st, t.d, t.nb(), L0.d, V(P->e), 0.0);
     launch_fill<TV>(st, t.d, t.nb(), L0.d, V(P->pk), 0.0);
+    if (P->net) launch_fill<TV>(st, t.d, t.nb(), L0.d, V(P->zp), 0.0);
     launch_dot<double, TV>(st, t.d, t.nb(), L0.d, V(P->rk), V(P->rk), P->partial);
     finish(t, P->r0n2);
     const double tol2 = rel_tol * rel_tol;
     std::vector<int> act(B);
+    const bool flex = P->net != nullptr;
+    bool use_net_solve = flex;
+    std::vector<double> rzh(B), rn_prev(B, 0.0);
+    HIPCHK(hipMemcpyAsync(rn_prev.data(), P->r0n2, B * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
     for (int it = 0; it < max_it; ++it) {
+      use_net = use_net_solve;
       vcycle(0, V(P->rk), V(P->zk));
       launch_dot<double, TV>(st, t.d, t.nb(), L0.d, V(P->rk), V(P->zk), P->partial);
       finish(t, P->rz_new);
+      if (flex) {
+        // Guard: a learned correction that is not a descent direction for
+        // some active instance is replaced by the plain V-cycle.
+        HIPCHK(hipMemcpyAsync(rzh.data(), P->rz_new, B * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(act.data(), P->active, B * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        bool bad = false;
+        for (int b = 0; b < B; ++b) bad |= act[b] && !(rzh[b] > 0);
+        if (bad) {
+          P->fallbacks += 1;
+          use_net = false;
+          vcycle(0, V(P->rk), V(P->zk));
+          launch_dot<double, TV>(st, t.d, t.nb(), L0.d, V(P->rk), V(P->zk), P->partial);
+          finish(t, P->rz_new);
+        }
+        use_net = use_net_solve;
+        // Polak-Ribiere (flexible) beta: (r.z - r.z_prev) / r_prev.z_prev
+        launch_dot<double, TV>(st, t.d, t.nb(), L0.d, V(P->rk), V(P->zp), P->partial);
+        finish(t, P->rzp);
+        launch_pcg_scalars(st, 3, B, it == 0, tol2, P->rz_new, P->rz, P->beta, P->rzp, P->alpha, P->rn2, P->r0n2,
+                           P->active, P->iters);
+        launch_copy_scale<TV, TV>(st, t.d, t.nb(), L0.d, V(P->zk), V(P->zp), nullptr, 0);
+      } else
       launch_pcg_scalars(st, 0, B, it == 0, tol2, P->rz_new, P->rz, P->beta, P->pq, P->alpha, P->rn2, P->r0n2,
                          P->active, P->iters);
       launch_update_p<TV>(st, t.d, t.nb(), L0.d, P->beta, V(P->zk), V(P->pk));
@@ -324,6 +549,21 @@ struct Solver {
       finish(t, P->rn2);
       launch_pcg_scalars(st, 2, B, 0, tol2, P->rz_new, P->rz, P->beta, P->pq, P->alpha, P->rn2, P->r0n2, P->active,
                          P->iters);
+      if (flex && use_net_solve && (it + 1) % 5 == 0) {
+        // Stagnation guard: if the learned correction reduced the residual
+        // more slowly than 0.8 per iteration over the last 5 iterations for
+        // any active instance, finish this solve with the plain V-cycle.
+        std::vector<double> rn(B);
+        HIPCHK(hipMemcpyAsync(rn.data(), P->rn2, B * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(act.data(), P->active, B * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        bool slow = false;
+        for (int b = 0; b < B; ++b)
+          if (act[b] && rn_prev[b] > 0 && rn[b] > 0.8 * 0.8 * 0.8 * 0.8 * 0.8 * 0.8 * 0.8 * 0.8 * 0.8 * 0.8 * rn_prev[b])
+            slow = true;
+        rn_prev = rn;
+        if (slow) { use_net_solve = false; P->fallbacks += 1; }
+      }
       if ((it + 1) % std::max(1, P->opt.check_every) == 0 || it + 1 == max_it) {
         HIPCHK(hipMemcpyAsync(act.data(), P->active, B * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -568,6 +808,7 @@ struct Solver {
     P->zk = P->alloc<TV>(n0);
     P->pk = P->alloc<TV>(n0);
     P->qk = P->alloc<TV>(n0);
+    P->zp = P->alloc<TV>(n0);
   }
 
   void coarsen_all() {
@@ -761,7 +1002,8 @@ void build_impl(mpde_problem* P, const mpde_desc* d) {
   S.alloc_vectors();
   const long long n0 = P->lv[0].npts;
   P->partial = P->alloc<double>(maxnb);
-  for (double** a : {&P->rz_new, &P->rz, &P->beta, &P->pq, &P->alpha, &P->rn2, &P->r0n2, &P->atd2, &P->scale, &P->iscale})
+  for (double** a : {&P->rz_new, &P->rz, &P->beta, &P->pq, &P->alpha, &P->rn2, &P->r0n2, &P->atd2, &P->scale,
+                     &P->iscale, &P->rzp})
     *a = P->alloc<double>(B);
   P->active = P->alloc<int>(B);
   P->iters = P->alloc<int>(B);
@@ -932,6 +1174,184 @@ int mpde_solve_adjoint(mpde_problem* p, const void* g_z, void* grad_coeff, void*
 
 
 void mpde_free(mpde_problem* p) { delete p; }
+
+int mpde_net_create(int32_t in_channels, uint64_t seed, mpde_net** out) {
+  g_err.clear();
+  if (!out) return fail(MPDE_ERR_INVALID_ARG, "out pointer is NULL");
+  *out = nullptr;
+  if (in_channels < 1 || in_channels > 16) return fail(MPDE_ERR_INVALID_ARG, "in_channels must be 1..16");
+  int rc = ensure_device();
+  if (rc) return rc;
+  mpde_net* n = new (std::nothrow) mpde_net();
+  if (!n) return fail(MPDE_ERR_OUT_OF_MEMORY, "host allocation failed");
+  n->cin = in_channels;
+  try {
+    auto al = [&](size_t cnt, size_t sz) {
+      void* p = nullptr;
+      HIPCHK(hipMalloc(&p, cnt * sz));
+      n->owned.push_back(p);
+      return p;
+    };
+    const size_t np = 3 * kLayerP;
+    n->w = (float*)al(np, 4); n->g = (float*)al(np, 4); n->m = (float*)al(np, 4); n->v = (float*)al(np, 4);
+    n->wb = (unsigned short*)al(3 * kLayerW, 2);
+    n->wtb = (unsigned short*)al(3 * kLayerW, 2);
+    n->partial = (float*)al((size_t)1024 * kLayerW, 4);
+    // He-scaled seeded initialisation (host), biases zero; weights on input
+    // channels >= in_channels of the first layer are zero.
+    std::vector<float> h(np, 0.f);
+    uint64_t st = seed * 6364136223846793005ULL + 1442695040888963407ULL;
+    auto rnd = [&]() {
+      st = st * 6364136223846793005ULL + 1442695040888963407ULL;
+      uint64_t z = st;
+      z ^= z >> 33; z *= 0xff51afd7ed558ccdULL; z ^= z >> 33;
+      return ((double)(z >> 11) / 9007199254740992.0) * 2.0 - 1.0;   // U(-1, 1)
+    };
+    for (int l = 0; l < 3; ++l) {
+      const int fan_in = 27 * (l == 0 ? in_channels : 16);
+      // the last layer starts at zero, so an untrained network is exactly
+      // the plain V-cycle
+      const double sc = l == 2 ? 0.0 : std::sqrt(6.0 / fan_in);
+      for (int tap = 0; tap < 27; ++tap)
+        for (int o = 0; o < 16; ++o)
+          for (int i = 0; i < 16; ++i) {
+            const bool live = (l > 0 || i < in_channels) && (l < 2 || o == 0);
+            h[l * kLayerP + (tap * 16 + o) * 16 + i] = live ? (float)(sc * rnd()) : 0.f;
+          }
+    }
+    HIPCHK(hipMemcpy(n->w, h.data(), np * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(n->m, 0, np * 4));
+    HIPCHK(hipMemset(n->v, 0, np * 4));
+    for (int k = 0; k < 3; ++k) pack_weights_launch(nullptr, n->w + k * kLayerP, n->wb + k * kLayerW, n->wtb + k * kLayerW);
+    HIPCHK(hipDeviceSynchronize());
+  } catch (const HipError& h) {
+    delete n;
+    return hip_fail(h);
+  }
+  *out = n;
+  return MPDE_OK;
+}
+
+void mpde_net_free(mpde_net* n) { delete n; }
+
+int mpde_net_get(const mpde_net* n, float* host, int64_t cnt) {
+  if (!n || !host || cnt < MPDE_NET_PARAMS) return fail(MPDE_ERR_INVALID_ARG, "bad net/host/size");
+  if (hipMemcpy(host, n->w, (size_t)MPDE_NET_PARAMS * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(MPDE_ERR_HIP, "copy failed");
+  return MPDE_OK;
+}
+
+int mpde_net_set(mpde_net* n, const float* host, int64_t cnt) {
+  if (!n || !host || cnt < MPDE_NET_PARAMS) return fail(MPDE_ERR_INVALID_ARG, "bad net/host/size");
+  if (hipMemcpy(n->w, host, (size_t)MPDE_NET_PARAMS * 4, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(MPDE_ERR_HIP, "copy failed");
+  for (int k = 0; k < 3; ++k) pack_weights_launch(nullptr, n->w + k * kLayerP, n->wb + k * kLayerW, n->wtb + k * kLayerW);
+  if (hipDeviceSynchronize() != hipSuccess) return fail(MPDE_ERR_HIP, "pack failed");
+  return MPDE_OK;
+}
+
+int mpde_net_train_step(mpde_net* n, mpde_problem* p, int32_t level, uint64_t seed, double lr, double* loss,
+                        double* loss_plain) {
+  g_err.clear();
+  if (!n || !p) return fail(MPDE_ERR_INVALID_ARG, "net or problem is NULL");
+  if (p->dtype != MPDE_F32) return fail(MPDE_ERR_UNSUPPORTED, "the learned correction runs on FP32 problems");
+  if (level < 1 || level >= (int)p->lv.size()) return fail(MPDE_ERR_INVALID_ARG, "level must be 1..levels-1");
+  if (2 + p->K > 16 || n->cin != 2 + p->K)
+    return fail(MPDE_ERR_INVALID_ARG, "network in_channels must equal 2 + number of coefficient fields");
+  if (!(lr > 0)) return fail(MPDE_ERR_INVALID_ARG, "lr must be > 0");
+  try {
+    Solver<float, float> S(p);
+    const double l = S.train_step(n, level, (unsigned)(seed * 2654435761u + 17u), lr, loss_plain);
+    if (loss) *loss = l;
+  } catch (const HipError& h) {
+    return hip_fail(h);
+  }
+  return MPDE_OK;
+}
+
+int mpde_net_attach(mpde_problem* p, const mpde_net* n, int32_t level) {
+  g_err.clear();
+  if (!p) return fail(MPDE_ERR_INVALID_ARG, "problem is NULL");
+  if (!n) { p->net = nullptr; return MPDE_OK; }
+  if (p->dtype != MPDE_F32) return fail(MPDE_ERR_UNSUPPORTED, "the learned correction runs on FP32 problems");
+  if (level < 1 || level >= (int)p->lv.size()) return fail(MPDE_ERR_INVALID_ARG, "level must be 1..levels-1");
+  if (n->cin != 2 + p->K) return fail(MPDE_ERR_INVALID_ARG, "network in_channels must equal 2 + K");
+  for (int b = 0; b < p->B; ++b)
+    if (p->nlev[b] <= level) return fail(MPDE_ERR_UNSUPPORTED, "every instance must have the network's level");
+  try {
+    Solver<float, float> S(p);
+    S.net_setup(level);
+  } catch (const HipError& h) {
+    return hip_fail(h);
+  }
+  p->net = n;
+  p->net_level = level;
+  return MPDE_OK;
+}
+
+int mpde_conv3d(const void* x, const void* w, const float* bias, float* y, void* yb, int32_t relu, int32_t sign,
+                int32_t batch, int32_t T, int32_t X, int32_t Y, const int32_t* periodic, void* stream) {
+  g_err.clear();
+  if (!x || !w || (!y && !yb) || !periodic || batch < 1 || T < 1 || X < 1 || Y < 1 || (sign != 1 && sign != -1))
+    return fail(MPDE_ERR_INVALID_ARG, "bad conv3d arguments");
+  int rc = ensure_device();
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const long long N = (long long)T * X * Y;
+  std::vector<mpde::Grid3> g(batch);
+  std::vector<int2> tiles;
+  for (int b = 0; b < batch; ++b) {
+    g[b] = mpde::Grid3{T, X, Y, {periodic[0], periodic[1], periodic[2]}, b * N};
+    for (long long s0 = 0; s0 < N; s0 += 16) tiles.push_back(make_int2(b, (int)s0));
+  }
+  while (tiles.size() % 4) tiles.push_back(make_int2(-1, 0));
+  void *dg = nullptr, *dt = nullptr;
+  if (hipMalloc(&dg, batch * sizeof(mpde::Grid3)) != hipSuccess || hipMalloc(&dt, tiles.size() * sizeof(int2)) != hipSuccess) {
+    (void)hipFree(dg);
+    return fail(MPDE_ERR_OUT_OF_MEMORY, "conv3d tables");
+  }
+  (void)hipMemcpyAsync(dg, g.data(), batch * sizeof(mpde::Grid3), hipMemcpyHostToDevice, st);
+  (void)hipMemcpyAsync(dt, tiles.data(), tiles.size() * sizeof(int2), hipMemcpyHostToDevice, st);
+  conv_launch(st, (int)tiles.size(), (const int2*)dt, (const mpde::Grid3*)dg, (const unsigned short*)x,
+              (const unsigned short*)w, bias, sign, y, (unsigned short*)yb, relu);
+  hipError_t e = hipStreamSynchronize(st);
+  (void)hipFree(dg);
+  (void)hipFree(dt);
+  return e == hipSuccess ? MPDE_OK : fail(MPDE_ERR_HIP, hipGetErrorString(e));
+}
+
+int mpde_conv3d_wgrad(const void* x, const void* dy, float* dw, int32_t batch, int32_t T, int32_t X, int32_t Y,
+                      const int32_t* periodic, void* stream) {
+  g_err.clear();
+  if (!x || !dy || !dw || !periodic || batch < 1 || T < 1 || X < 1 || Y < 1)
+    return fail(MPDE_ERR_INVALID_ARG, "bad conv3d_wgrad arguments");
+  int rc = ensure_device();
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const long long N = (long long)T * X * Y;
+  std::vector<mpde::Grid3> g(batch);
+  std::vector<int2> tiles;
+  for (int b = 0; b < batch; ++b) {
+    g[b] = mpde::Grid3{T, X, Y, {periodic[0], periodic[1], periodic[2]}, b * N};
+    for (long long s0 = 0; s0 < N; s0 += 16) tiles.push_back(make_int2(b, (int)s0));
+  }
+  void *dg = nullptr, *dt = nullptr, *part = nullptr;
+  if (hipMalloc(&dg, batch * sizeof(mpde::Grid3)) != hipSuccess || hipMalloc(&dt, tiles.size() * sizeof(int2)) != hipSuccess ||
+      hipMalloc(&part, (size_t)1024 * kLayerW * 4) != hipSuccess) {
+    (void)hipFree(dg);
+    (void)hipFree(dt);
+    return fail(MPDE_ERR_OUT_OF_MEMORY, "conv3d_wgrad tables");
+  }
+  (void)hipMemcpyAsync(dg, g.data(), batch * sizeof(mpde::Grid3), hipMemcpyHostToDevice, st);
+  (void)hipMemcpyAsync(dt, tiles.data(), tiles.size() * sizeof(int2), hipMemcpyHostToDevice, st);
+  conv_wgrad_launch(st, (int)tiles.size(), (const int2*)dt, (const mpde::Grid3*)dg, (const unsigned short*)x,
+                    (const unsigned short*)dy, (float*)part, dw);
+  hipError_t e = hipStreamSynchronize(st);
+  (void)hipFree(dg);
+  (void)hipFree(dt);
+  (void)hipFree(part);
+  return e == hipSuccess ? MPDE_OK : fail(MPDE_ERR_HIP, hipGetErrorString(e));
+}
 
 int mpde_kernel_stats(const mpde_problem* p, mpde_kstat* out, int32_t max) {
   if (!p || !p->opt.profile) return 0;

@@ -995,6 +995,11 @@ __global__ void k_pcg_scalars(int op, int B, int first, double tol2, double* __r
   } else if (op == 1) {
     const double d = pq[b];
     alpha[b] = (active[b] && d > 0.0 && isfinite(d)) ? rz[b] / d : 0.0;
+  } else if (op == 3) {
+    // flexible (Polak-Ribiere) beta; pq carries r.z_prev
+    const double v = rz_new[b];
+    beta[b] = (active[b] && !first && rz[b] != 0.0) ? (v - pq[b]) / rz[b] : 0.0;
+    rz[b] = v;
   } else {
     if (active[b]) {
       iters[b] += 1;
@@ -1677,6 +1682,8 @@ template void launch_copy_scale<double, float>(hipStream_t, const Work*, int, co
                                                const double*, int);
 template void launch_copy_scale<float, double>(hipStream_t, const Work*, int, const LInst*, const float*, double*,
                                                const double*, int);
+template void launch_copy_scale<float, float>(hipStream_t, const Work*, int, const LInst*, const float*, float*,
+                                              const double*, int);
 template void launch_copy_scale<double, double>(hipStream_t, const Work*, int, const LInst*, const double*,
                                                 double*, const double*, int);
 template void launch_atd_norm<float>(int, hipStream_t, const Work*, int, const LInst*, CIdx, const float*,

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     src = open(os.path.join(ROOT, "include", "mpde.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return set(re.findall(r"\b(mpde_[a-z_]+)\s*\(", src))
+    return set(re.findall(r"\b(mpde_[a-z0-9_]+)\s*\(", src))
 
 
 def test_exports_match_header():
