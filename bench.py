@@ -85,6 +85,10 @@ def main():
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="do not time kernels with events")
+    ap.add_argument("--no-single", action="store_true", help="ragged: skip the one-problem-per-instance baseline")
+    ap.add_argument("--workload", choices=["rd2d", "ragged"], default="rd2d",
+                    help="rd2d: 64 x 32x64x64 reaction-diffusion (default); ragged: 256 ragged 1D+time instances, "
+                         "batched vs one problem per instance")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); instances of a batch are "
@@ -97,6 +101,8 @@ def main():
     from paper_2502_18377_amd.api import Problem, pack
 
     dev = torch.device("cuda:0")
+    if args.workload == "ragged":
+        return bench_ragged(args, np, torch, W, Problem, pack, dev)
     B = args.batch
     insts = [W.reaction_diffusion_2d(i) for i in range(B)]
     pk = pack(insts, dtype=torch.float32, device=dev)
@@ -159,6 +165,73 @@ def main():
            "max_relres": max(relres), "roofline": roof}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+def bench_ragged(args, np, torch, W, Problem, pack, dev):
+    """Batching form: 256 instances of the 1D+time workload with each axis
+    drawn from {16,24,32,48,64}, FP32, solved in one batch (one launch per
+    stage for all instances) vs one problem per instance."""
+    from paper_2502_18377_amd import autotune
+    B = 256 if args.batch == 64 else args.batch
+    shapes = W.ragged_shapes(B)
+    insts = [W.reaction_diffusion_1d_ragged(i, s) for i, s in enumerate(shapes)]
+    pk = pack(insts, dtype=torch.float32, device=dev)
+    singles = [pack([inst], dtype=torch.float32, device=dev) for inst in insts]
+    torch.cuda.synchronize()
+    # autotuned settings for this shape class (searched once, outside the timed region)
+    tp = Problem(pk["coeff"], pk["rhs"], pk["bc_values"], pk["shapes"], pk["steps"], pk["bc"], pk["mset"])
+    tuned = autotune.run(tp)
+    tp.close()
+    topts = {k: tuned[k] for k in ("nu", "check_every", "inner_tol")}
+
+    def batched():
+        prob = Problem(pk["coeff"], pk["rhs"], pk["bc_values"], pk["shapes"], pk["steps"], pk["bc"], pk["mset"],
+                       **topts)
+        z, info = prob.solve()
+        prob.close()
+        if info["code"] != 0:
+            raise SystemExit(f"batched solve did not converge: {info}")
+        return info
+
+    def one_by_one():
+        its = []
+        for q in singles:
+            prob = Problem(q["coeff"], q["rhs"], q["bc_values"], q["shapes"], q["steps"], q["bc"], q["mset"])
+            z, info = prob.solve()
+            prob.close()
+            its.append(info["iters"][0])
+        return its
+
+    for _ in range(args.warmup):
+        batched()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        info = batched()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if args.no_single:
+        t2, its1, t3 = 0.0, [0], 1.0
+    else:
+        one_by_one()                    # warm
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        its1 = one_by_one()
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+    value = B * args.steps / (t1 - t0)
+    single = B / (t3 - t2) if not args.no_single else None
+    out = {"metric": METRIC, "value": round(value, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round((t1 - t0) * 1000 / args.steps, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "256 ragged 1D+time reaction-advection-diffusion instances, each axis in "
+                                  "{16,24,32,48,64}, FP32, build+solve to 1e-6, one batch",
+                      "batch": B, "solver": "plain multigrid-PCG, captured HIP graphs", "autotuned": tuned},
+           "one_problem_per_instance": None if single is None else
+           {"value": round(single, 3), "unit": "solves/s", "mean_pcg_iters": round(float(np.mean(its1)), 2)},
+           "batched_over_single": None if single is None else round(value / single, 2),
+           "mean_pcg_iters": round(float(info["iters"].mean()), 2), "max_relres": float(info["relres"].max())}
     print(json.dumps(out), flush=True)
 
 

@@ -90,7 +90,10 @@ typedef struct {
                             mpde_solve with HIP events (see mpde_kernel_stats) */
   int32_t out_f64;       /* nonzero: mpde_solve writes z_out as FP64 (the FP64
                             iterate) even for an MPDE_F32 problem (0) */
-  int32_t reserved[6];
+  int32_t graph;         /* nonzero: replay the Krylov iterations between
+                            host convergence checks as captured HIP graphs
+                            (1; ignored while profiling or with a network) */
+  int32_t reserved[5];
 } mpde_options;
 
 /* Problem description (the encoder outputs of Eq. 2 with uniform steps). */
@@ -237,6 +240,14 @@ int mpde_conv3d(const void *x_bf16, const void *w_bf16, const float *bias, float
  * sum over points of dy[p][out] * x[p + off(tap)][in]. */
 int mpde_conv3d_wgrad(const void *x_bf16, const void *dy_bf16, float *dw, int32_t batch, int32_t T, int32_t X,
                       int32_t Y, const int32_t *periodic, void *stream);
+
+/* Autotuner: time complete solves of p for candidate settings of the
+ * smoothing steps (nu), the inner Krylov tolerance and the number of Krylov
+ * iterations per captured graph / host check, by coordinate search, and keep
+ * the fastest in p's options.  chosen (host, may be NULL) receives
+ * {nu, check_every, inner_tol * 1e9} of the winner; *best_ms its solve time.
+ * The solution state of p is overwritten (call mpde_solve afterwards). */
+int mpde_autotune(mpde_problem *p, void *z_scratch, int32_t *chosen, double *best_ms);
 
 /* Grid levels planned for instance b (0 if p is NULL or b out of range);
  * if shapes is not NULL it receives levels*D points-per-axis values. */

@@ -15,7 +15,7 @@ BC_CODES = {"none": MPDE_BC_NONE, "dirichlet": MPDE_BC_DIRICHLET, "periodic": MP
 EXPORTS = ("mpde_default_options", "mpde_build", "mpde_solve", "mpde_solve_adjoint",
            "mpde_free", "mpde_last_error", "mpde_levels", "mpde_kernel_stats",
            "mpde_net_create", "mpde_net_train_step", "mpde_net_attach", "mpde_net_get", "mpde_net_set",
-           "mpde_net_free", "mpde_conv3d", "mpde_conv3d_wgrad")
+           "mpde_net_free", "mpde_conv3d", "mpde_conv3d_wgrad", "mpde_autotune")
 NET_PARAMS = 3 * (27 * 16 * 16 + 16)
 
 
@@ -24,7 +24,7 @@ class Options(ctypes.Structure):
                 ("max_outer", ctypes.c_int32), ("max_inner", ctypes.c_int32),
                 ("nu", ctypes.c_int32), ("coarse_min", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("max_levels", ctypes.c_int32),
-                ("profile", ctypes.c_int32), ("out_f64", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("profile", ctypes.c_int32), ("out_f64", ctypes.c_int32), ("graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class KStat(ctypes.Structure):
@@ -91,7 +91,8 @@ def load():
     lib.mpde_net_free.restype = None
     lib.mpde_conv3d.argtypes = [vp, vp, vp, vp, vp, i32, i32, i32, i32, i32, i32, ctypes.POINTER(i32), vp]
     lib.mpde_conv3d_wgrad.argtypes = [vp, vp, vp, i32, i32, i32, i32, ctypes.POINTER(i32), vp]
-    for f in ("mpde_net_create", "mpde_net_train_step", "mpde_net_attach", "mpde_net_get", "mpde_net_set",
+    lib.mpde_autotune.argtypes = [vp, vp, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
+    for f in ("mpde_autotune", "mpde_net_create", "mpde_net_train_step", "mpde_net_attach", "mpde_net_get", "mpde_net_set",
               "mpde_conv3d", "mpde_conv3d_wgrad"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib

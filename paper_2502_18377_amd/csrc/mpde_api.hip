@@ -114,7 +114,7 @@ struct Level {
   std::vector<int> cinst64, cinstg;   // coarsest here: 64-point planes / other planes
   int *d_cinst64 = nullptr, *d_cinstg = nullptr;
   void* coef = nullptr;        // TC [K planes per instance]
-  void *x = nullptr, *r = nullptr, *dd = nullptr, *b = nullptr, *gam = nullptr, *dinv = nullptr;
+  void *x = nullptr, *r = nullptr, *dd = nullptr, *dd2 = nullptr, *b = nullptr, *gam = nullptr, *dinv = nullptr;
 };
 
 }  // namespace
@@ -177,6 +177,16 @@ struct mpde_problem {
   void* zp = nullptr;                                      // previous z (flexible CG)
   double* rzp = nullptr;
   long long fallbacks = 0;                                 // learned -> plain V-cycle switches
+  // captured Krylov chunks (first chunk of a solve / later chunks)
+  hipStream_t gst = nullptr;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  int gkey[2] = {0, 0};                                    // (nu, chunk) the graphs were captured with
+  hipEvent_t gev[2] = {nullptr, nullptr};
+  double gtol = -1;
+  void drop_graphs() {
+    for (auto& g : gexec)
+      if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+  }
   // profiling (options.profile): event pairs around finest-grid kernels
   struct Rec { int kind; hipEvent_t a, b; double bytes; };
   std::vector<Rec> recs;
@@ -193,6 +203,9 @@ struct mpde_problem {
   }
   std::vector<void*> owned;
   ~mpde_problem() {
+    drop_graphs();
+    for (hipEvent_t e : gev) if (e) (void)hipEventDestroy(e);
+    if (gst) (void)hipStreamDestroy(gst);
     for (void* p : owned) (void)hipFree(p);
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
   }
@@ -453,16 +466,21 @@ struct Solver {
     pend(l, 1, t, mode);
   }
 
+  // nu Chebyshev steps; the search direction is double-buffered (dd / dd2):
+  // each step reads d at stencil neighbours, so the new direction must go to
+  // the other buffer.  The start direction is in dd.
   void chebyshev(int l, TV* x, int nu) {
     Level& L = P->lv[l];
     const Table& t = L.smooth;
     for (int s = 0; s < nu; ++s) {
+      TV* cur = V((s & 1) ? L.dd2 : L.dd);
+      TV* nxt = V((s & 1) ? L.dd : L.dd2);
       pbeg(l);
-      launch_gamma<TV, TV, TC>(D, st, t.d, t.nb(), L.d, P->ci, V(L.dd), C(L.coef), C(P->f), 0, V(L.gam));
+      launch_gamma<TV, TV, TC>(D, st, t.d, t.nb(), L.d, P->ci, cur, C(L.coef), C(P->f), 0, V(L.gam));
       pend(l, 0, t, 0);
       pbeg(l);
-      launch_gather<TV, TV, TC>(D, st, t.d, t.nb(), L.d, P->ci, V(L.dd), V(L.gam), C(L.coef), C(P->w), 0, G_CHEB,
-                                nullptr, nullptr, x, V(L.r), V(L.dd), V(L.dinv), s, nullptr);
+      launch_gather<TV, TV, TC>(D, st, t.d, t.nb(), L.d, P->ci, cur, V(L.gam), C(L.coef), C(P->w), 0, G_CHEB,
+                                nullptr, nullptr, x, V(L.r), nxt, V(L.dinv), s, nullptr);
       pend(l, 1, t, G_CHEB);
     }
   }
@@ -493,6 +511,62 @@ struct Solver {
     chebyshev(l, x, nu);
   }
 
+  // One PCG iteration (plain V-cycle preconditioner, no host interaction).
+  void pcg_iter(bool first, double tol2) {
+    Level& L0 = P->lv[0];
+    const Table& t = L0.all;
+    const int B = P->B;
+    vcycle(0, V(P->rk), V(P->zk));
+    launch_dot<double, TV>(st, t.d, t.nb(), L0.d, V(P->rk), V(P->zk), P->partial);
+    finish(t, P->rz_new);
+    launch_pcg_scalars(st, 0, B, first, tol2, P->rz_new, P->rz, P->beta, P->pq, P->alpha, P->rn2, P->r0n2,
+                       P->active, P->iters);
+    launch_update_p<TV>(st, t.d, t.nb(), L0.d, P->beta, V(P->zk), V(P->pk));
+    apply(0, t, V(P->pk), V(P->qk), G_STORE_DOT, P->partial);
+    finish(t, P->pq);
+    launch_pcg_scalars(st, 1, B, 0, tol2, P->rz_new, P->rz, P->beta, P->pq, P->alpha, P->rn2, P->r0n2, P->active,
+                       P->iters);
+    launch_update_xr<TV>(st, t.d, t.nb(), L0.d, P->alpha, V(P->pk), V(P->qk), V(P->e), V(P->rk), P->partial);
+    finish(t, P->rn2);
+    launch_pcg_scalars(st, 2, B, 0, tol2, P->rz_new, P->rz, P->beta, P->pq, P->alpha, P->rn2, P->r0n2, P->active,
+                       P->iters);
+  }
+
+  // Run `chunk` iterations through a captured graph (captured on first use
+  // for this (nu, chunk, tolerance) and replayed afterwards).
+  void pcg_chunk_graph(int which, int chunk, double tol2) {
+    const int key = (P->opt.nu * 1000 + chunk) * 2 + which;
+    if (!P->gst) {
+      HIPCHK(hipStreamCreateWithFlags(&P->gst, hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&P->gev[0], hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&P->gev[1], hipEventDisableTiming));
+    }
+    if (P->gexec[which] && (P->gkey[which] != key || P->gtol != tol2)) {
+      (void)hipGraphExecDestroy(P->gexec[which]);
+      P->gexec[which] = nullptr;
+    }
+    HIPCHK(hipEventRecord(P->gev[0], st));
+    HIPCHK(hipStreamWaitEvent(P->gst, P->gev[0], 0));
+    if (!P->gexec[which]) {
+      hipStream_t keep = st;
+      st = P->gst;
+      HIPCHK(hipStreamBeginCapture(P->gst, hipStreamCaptureModeThreadLocal));
+      for (int k = 0; k < chunk; ++k) pcg_iter(which == 0 && k == 0, tol2);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(P->gst, &g);
+      st = keep;
+      if (e != hipSuccess) throw HipError{e, "hipStreamEndCapture"};
+      e = hipGraphInstantiate(&P->gexec[which], g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) throw HipError{e, "hipGraphInstantiate"};
+      P->gkey[which] = key;
+      P->gtol = tol2;
+    }
+    HIPCHK(hipGraphLaunch(P->gexec[which], P->gst));
+    HIPCHK(hipEventRecord(P->gev[1], P->gst));
+    HIPCHK(hipStreamWaitEvent(st, P->gev[1], 0));
+  }
+
   // PCG on S e = rk (level 0), e = 0 start; instances with active=0 stay frozen.
   void pcg(double rel_tol, int max_it) {
     Level& L0 = P->lv[0];
@@ -505,6 +579,18 @@ struct Solver {
     finish(t, P->r0n2);
     const double tol2 = rel_tol * rel_tol;
     std::vector<int> act(B);
+    const int chunk = std::max(1, P->opt.check_every);
+    if (P->opt.graph && !P->opt.profile && !P->net) {
+      for (int it = 0; it < max_it; it += chunk) {
+        pcg_chunk_graph(it == 0 ? 0 : 1, chunk, tol2);
+        HIPCHK(hipMemcpyAsync(act.data(), P->active, B * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        bool any = false;
+        for (int b = 0; b < B; ++b) any |= act[b] != 0;
+        if (!any) break;
+      }
+      return;
+    }
     const bool flex = P->net != nullptr;
     bool use_net_solve = flex;
     std::vector<double> rzh(B), rn_prev(B, 0.0);
@@ -796,6 +882,7 @@ struct Solver {
       L.x = P->alloc<TV>(L.npts);
       L.r = P->alloc<TV>(L.npts);
       L.dd = P->alloc<TV>(L.npts);
+      L.dd2 = P->alloc<TV>(L.npts);
       L.b = P->alloc<TV>(L.npts);
       L.gam = P->alloc<TV>(L.npts);
       L.dinv = P->alloc<TV>(L.npts);
@@ -1093,6 +1180,7 @@ int mpde_default_options(mpde_options* o) {
   o->coarse_min = 8;
   o->check_every = 2;
   o->max_levels = 16;
+  o->graph = 1;
   return MPDE_OK;
 }
 
@@ -1351,6 +1439,55 @@ int mpde_conv3d_wgrad(const void* x, const void* dy, float* dw, int32_t batch, i
   (void)hipFree(dt);
   (void)hipFree(part);
   return e == hipSuccess ? MPDE_OK : fail(MPDE_ERR_HIP, hipGetErrorString(e));
+}
+
+int mpde_autotune(mpde_problem* p, void* z, int32_t* chosen, double* best_ms) {
+  g_err.clear();
+  if (!p || !z) return fail(MPDE_ERR_INVALID_ARG, "problem or z_scratch is NULL");
+  auto timed = [&](double& ms) -> int {
+    int rc = 0;
+    for (int rep = 0; rep < 2; ++rep) {        // first run captures graphs; time the second
+      auto t0 = std::chrono::steady_clock::now();
+      try {
+        rc = p->dtype == MPDE_F32 ? solve_impl<float, float>(p, z, nullptr) : solve_impl<double, double>(p, z, nullptr);
+      } catch (const HipError& h) {
+        return hip_fail(h);
+      }
+      ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return rc;
+  };
+  const mpde_options keep = p->opt;
+  double best;
+  int rc = timed(best);
+  if (rc < 0) return rc;
+  if (rc != MPDE_OK) best = 1e300;
+  mpde_options cur = p->opt;
+  const std::vector<double> tols = p->dtype == MPDE_F32 ? std::vector<double>{1e-2, 1e-3, 1e-4}
+                                                         : std::vector<double>{1e-6, 1e-8, 1e-10};
+  for (int pass = 0; pass < 3; ++pass) {
+    std::vector<mpde_options> cands;
+    for (int v : {1, 2, 3, 4}) if (pass == 0) { mpde_options o = cur; o.nu = v; cands.push_back(o); }
+    for (double t : tols) if (pass == 1) { mpde_options o = cur; o.inner_tol = t; cands.push_back(o); }
+    for (int c : {2, 4, 8, 16}) if (pass == 2) { mpde_options o = cur; o.check_every = c; cands.push_back(o); }
+    for (const auto& o : cands) {
+      p->opt = o;
+      double ms;
+      rc = timed(ms);
+      if (rc < 0) { p->opt = keep; return rc; }
+      if (rc == MPDE_OK && ms < best) { best = ms; cur = o; }
+    }
+    p->opt = cur;
+  }
+  p->opt = cur;
+  p->opt.tol = keep.tol;
+  if (chosen) {
+    chosen[0] = cur.nu;
+    chosen[1] = cur.check_every;
+    chosen[2] = (int32_t)std::lround((cur.inner_tol > 0 ? cur.inner_tol : (p->dtype == MPDE_F32 ? 1e-4 : 1e-10)) * 1e9);
+  }
+  if (best_ms) *best_ms = best;
+  return MPDE_OK;
 }
 
 int mpde_kernel_stats(const mpde_problem* p, mpde_kstat* out, int32_t max) {

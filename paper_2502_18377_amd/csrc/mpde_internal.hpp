@@ -72,7 +72,8 @@ struct Work {
 enum GatherMode {
   G_STORE = 0,      // out = S u (- g when sigma = 1)
   G_RESID = 1,      // out = b - y (b may be null), d = dinv*out/theta if d != null
-  G_CHEB = 2,       // Chebyshev step on (x, r, d = u): x += d, r -= y, d = a d + c dinv r
+  G_CHEB = 2,       // Chebyshev step on (x, r, d = u): x += d, r -= y, d' = a d + c dinv r;
+                    // d' must not alias u (neighbours of u are still being read)
   G_STORE_DOT = 3,  // out = y and per-block partial sum of u*y
 };
 

@@ -126,3 +126,48 @@ def test_rd2d_full_size_residual():
     _, z32, _ = gpu_solve(insts[:2], "f32")
     for b in range(2):
         assert rel(z32[b], zs[b]) <= 2e-7
+
+
+def test_graph_replay_matches_eager():
+    # Captured Krylov chunks replayed several times, with eager solves in
+    # between, give the same iterates as the eager path.
+    shapes = [(16, 24), (32, 16), (24, 48)]
+    insts = [as_dtype(W.reaction_diffusion_1d_ragged(i, s), "f32") for i, s in enumerate(shapes)]
+    pg, zg, ig = gpu_solve(insts, "f32", graph=1, check_every=4)
+    pe, ze, ie = gpu_solve(insts, "f32", graph=0, check_every=4)
+    for _ in range(2):
+        z2, i2 = pg.solve()
+        z3, i3 = pe.solve()
+        assert np.array_equal(z2.cpu().numpy(), z3.cpu().numpy())
+        assert np.array_equal(i2["iters"], i3["iters"])
+    for a, b in zip(zg, ze):
+        assert np.array_equal(a, b)
+
+
+def test_autotune_keeps_a_converging_setting():
+    from paper_2502_18377_amd import autotune
+    shapes = [(16, 24), (32, 16), (24, 48), (48, 32)]
+    insts = [as_dtype(W.reaction_diffusion_1d_ragged(i, s), "f32") for i, s in enumerate(shapes)]
+    prob, zs, info = gpu_solve(insts, "f32")
+    ch = autotune.run(prob)
+    assert ch["nu"] in (1, 2, 3, 4) and ch["check_every"] in (2, 4, 8, 16)
+    z, info2 = prob.solve()
+    assert info2["code"] == 0 and np.all(info2["relres"] <= 1e-6)
+    zs2 = prob.split(z)
+    for a, inst in zip(zs2, insts):
+        assert rel(a.double().cpu().numpy(), oracle_solve(inst)[0]) <= 1e-4
+
+
+@pytest.mark.parametrize("maker", [lambda: [W.reaction_diffusion_1d_ragged(0, (16, 24)), W.reaction_diffusion_1d_ragged(1, (12, 12))],
+                                   lambda: [W.reaction_diffusion_2d(i, shape=(16, 32, 32)) for i in range(2)]])
+def test_repeated_solves_bitwise_identical(maker):
+    # All reductions run in a fixed order and no kernel reads what another
+    # thread of the same launch writes (the smoother's search direction is
+    # double-buffered), so repeated solves of one problem are bitwise equal.
+    insts = [as_dtype(i, "f32") for i in maker()]
+    prob, zs, info = gpu_solve(insts, "f32", graph=0)
+    for _ in range(2):
+        z, inf2 = prob.solve()
+        for a, b in zip(prob.split(z), zs):
+            assert np.array_equal(a.double().cpu().numpy(), b)
+        assert np.array_equal(inf2["iters"], info["iters"])
