@@ -29,12 +29,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "PDE solves/sec to 1e-6 rel. residual, learned vs plain MG; stencil HBM GB/s"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_2502_18377_amd", "csrc", "mpde_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_2502_18377_amd", "csrc")
+KERNEL_SRC = {"apply3": "mpde_fused.hip", "gamma": "mpde_kernels.hip", "gather": "mpde_kernels.hip"}
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic_rd2d_64x32x64x64.json")
 
 
-def kernel_source_sha():
-    with open(KERNEL_SRC, "rb") as f:
+def kernel_source_sha(kernel):
+    with open(os.path.join(CSRC, KERNEL_SRC[kernel]), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
@@ -47,10 +48,10 @@ def traffic_for(kernel, launches_per_step_bytes):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("source_sha") != kernel_source_sha():
-        return None
     k = t.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("bytes_per_launch")
+    if k is None or k.get("source_sha") != kernel_source_sha(kernel):
+        return None
+    return k.get("bytes_per_launch")
 
 
 def cpu_baseline(seconds=12.0, max_instances=8):
@@ -132,6 +133,8 @@ def main():
         if info["code"] != 0:
             raise SystemExit(f"solve did not converge: {info}")
         for k, v in ks.items():
+            if v["launches"] == 0:
+                continue
             a = kstat.setdefault(k, dict(launches=0, ms=0.0, bytes=0.0))
             for f in a:
                 a[f] += v[f]

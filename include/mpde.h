@@ -93,7 +93,11 @@ typedef struct {
   int32_t graph;         /* nonzero: replay the Krylov iterations between
                             host convergence checks as captured HIP graphs
                             (1; ignored while profiling or with a network) */
-  int32_t reserved[5];
+  int32_t fused;         /* nonzero: FP32 levels with three axes (t, x, y), x
+                            and y periodic, use the one-pass operator kernel
+                            that evaluates every row once (1); zero: the
+                            two-pass kernels (same operator, other rounding) */
+  int32_t reserved[4];
 } mpde_options;
 
 /* Problem description (the encoder outputs of Eq. 2 with uniform steps). */

@@ -24,7 +24,8 @@ class Options(ctypes.Structure):
                 ("max_outer", ctypes.c_int32), ("max_inner", ctypes.c_int32),
                 ("nu", ctypes.c_int32), ("coarse_min", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("max_levels", ctypes.c_int32),
-                ("profile", ctypes.c_int32), ("out_f64", ctypes.c_int32), ("graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("profile", ctypes.c_int32), ("out_f64", ctypes.c_int32), ("graph", ctypes.c_int32), ("fused", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class KStat(ctypes.Structure):

@@ -14,7 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpde.so")
-SOURCES = ["mpde_kernels.hip", "mpde_conv.hip", "mpde_api.hip"]
+SOURCES = ["mpde_kernels.hip", "mpde_fused.hip", "mpde_conv.hip", "mpde_api.hip"]
 ARCH = os.environ.get("MPDE_OFFLOAD_ARCH", "gfx950")
 
 

@@ -29,11 +29,13 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/mpde.h"
 #include "mpde_internal.hpp"
 #include "mpde_kernels.hpp"
+#include "mpde_fused.hpp"
 #include "mpde_conv.hpp"
 
 using namespace mpde;
@@ -106,13 +108,26 @@ struct Table {
   int nb() const { return (int)h.size(); }
 };
 
+// Tiles of the fused three-axis operator over the selected instances, with
+// per-instance ranges of block-partial slots (FTile.pad).
+struct FTab {
+  std::vector<FTile> h;
+  std::vector<int> bstart;     // [B+1] over partial slots
+  FGeom g{};
+  bool ok = false;             // every selected instance fits the fused kernel
+  FTile* d = nullptr;
+  int* d_bstart = nullptr;
+  int nb() const { return (int)h.size(); }
+};
+
 struct Level {
   std::vector<LInst> h;        // [B]; N = 0 for instances without this level
   LInst* d = nullptr;
   long long npts = 0;          // total points of this level
   Table all, smooth, dense;    // all instances / non-coarsest / coarsest (rows)
-  std::vector<int> cinst64, cinstg;   // coarsest here: 64-point planes / other planes
-  int *d_cinst64 = nullptr, *d_cinstg = nullptr;
+  FTab fall, fsmooth;          // fused-operator tiles for `all` and `smooth`
+  std::vector<int> cinst64, cinst16, cinstg;   // coarsest here: 64-point / <= 16-point / other planes
+  int *d_cinst64 = nullptr, *d_cinst16 = nullptr, *d_cinstg = nullptr;
   void* coef = nullptr;        // TC [K planes per instance]
   void *x = nullptr, *r = nullptr, *dd = nullptr, *dd2 = nullptr, *b = nullptr, *gam = nullptr, *dinv = nullptr;
 };
@@ -192,7 +207,7 @@ struct mpde_problem {
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
   size_t pool_used = 0;
-  mpde_kstat kst[2]{};
+  mpde_kstat kst[3]{};
   hipEvent_t ev() {
     if (pool_used == pool.size()) {
       hipEvent_t e;
@@ -238,6 +253,91 @@ void make_table(Table& t, const std::vector<LInst>& h, int B, const std::vector<
     t.npts += h[b].N;
   }
   t.bstart[B] = (int)t.h.size();
+}
+
+// Tiles of the fused operator: each selected instance is cut into (TX, TY)
+// tiles of its (x, y) plane; TX and TY are common to the level and chosen so
+// that the rows of a tile plus halo fit one block (kFThreads points) and the
+// level has at least ~2 blocks per compute unit where the shapes allow.
+// Consecutive groups of 8 instances are interleaved tile by tile, so that
+// with round-robin block dispatch all tiles of one instance (which share
+// halos) run on the same XCD and its L2.
+void make_ftab(FTab& f, const std::vector<LInst>& h, int B, const std::vector<int>& sel, int D) {
+  f.h.clear();
+  f.bstart.assign(B + 1, 0);
+  f.ok = false;
+  if (D != 3) return;
+  int nsel = 0, mnx = 0, mny = 0;
+  for (int b = 0; b < B; ++b) {
+    if (!sel[b] || h[b].N == 0) continue;
+    const LInst& q = h[b];
+    if (q.per[0] || !q.per[1] || !q.per[2] || q.n[0] < 5 || q.n[1] < 4 || q.n[2] < 4) return;
+    ++nsel;
+    mnx = std::max(mnx, q.n[1]);
+    mny = std::max(mny, q.n[2]);
+  }
+  if (nsel == 0) return;
+  auto fits = [&](int TX, int TY) {
+    for (int b = 0; b < B; ++b) {
+      if (!sel[b] || h[b].N == 0) continue;
+      const LInst& q = h[b];
+      for (int x0 = 0; x0 < q.n[1]; x0 += TX)
+        for (int y0 = 0; y0 < q.n[2]; y0 += TY) {
+          const FSpan X = fspan(x0, TX, q.n[1], 1), Y = fspan(y0, TY, q.n[2], 1);
+          if (X.qn * Y.qn > kFThreads || X.un * Y.un > 2 * kFThreads) return false;
+        }
+    }
+    return true;
+  };
+  auto count = [&](int TX, int TY) {
+    long long n = 0;
+    for (int b = 0; b < B; ++b)
+      if (sel[b] && h[b].N > 0) n += (long long)((h[b].n[1] + TX - 1) / TX) * ((h[b].n[2] + TY - 1) / TY);
+    return n;
+  };
+  int TY = std::min(mny, 64), TX = 0;
+  for (;; TY = std::max(1, TY / 2)) {
+    for (int t = mnx; t >= 1; --t)
+      if (mnx % t == 0 && fits(t, TY)) { TX = t; break; }
+    if (TX > 0 || TY == 1) break;
+  }
+  if (TX == 0) return;
+  while (count(TX, TY) < 512 && TX % 2 == 0 && TX / 2 >= 4 && fits(TX / 2, TY)) TX /= 2;
+  f.g.TX = TX;
+  f.g.TY = TY;
+  f.g.uplane = f.g.qplane = 0;
+  std::vector<std::vector<FTile>> per(B);
+  int slot = 0;
+  for (int b = 0; b < B; ++b) {
+    f.bstart[b] = slot;
+    if (!sel[b] || h[b].N == 0) continue;
+    const LInst& q = h[b];
+    for (int x0 = 0; x0 < q.n[1]; x0 += TX)
+      for (int y0 = 0; y0 < q.n[2]; y0 += TY) {
+        const FSpan X = fspan(x0, TX, q.n[1], 1), Y = fspan(y0, TY, q.n[2], 1);
+        f.g.uplane = std::max(f.g.uplane, X.un * Y.un);
+        f.g.qplane = std::max(f.g.qplane, X.qs * Y.qs);
+        per[b].push_back(FTile{b, x0, y0, slot++});
+      }
+  }
+  f.bstart[B] = slot;
+  if (sizeof(float) * (2 * (size_t)f.g.uplane + 16 * (size_t)f.g.qplane) > 65536) return;   // LDS per block
+  for (int g0 = 0; g0 < B; g0 += 8) {
+    size_t mt = 0;
+    for (int b = g0; b < std::min(B, g0 + 8); ++b) mt = std::max(mt, per[b].size());
+    for (size_t t = 0; t < mt; ++t)
+      for (int b = g0; b < std::min(B, g0 + 8); ++b)
+        if (t < per[b].size()) f.h.push_back(per[b][t]);
+  }
+  f.ok = true;
+}
+
+void upload_ftab(mpde_problem* P, FTab& f) {
+  if (!f.ok) return;
+  f.d = P->alloc<FTile>(f.h.size());
+  f.d_bstart = P->alloc<int>(f.bstart.size());
+  HIPCHK(hipMemcpy(f.d, f.h.data(), f.h.size() * sizeof(FTile), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(f.d_bstart, f.bstart.data(), f.bstart.size() * sizeof(int), hipMemcpyHostToDevice));
 }
 
 template <typename TV>
@@ -414,7 +514,8 @@ struct Solver {
 
   void finish(const Table& t, double* out) { launch_finish_sum(st, P->partial, t.d_bstart, P->B, out); }
 
-  // Profiling of finest-grid kernels: kind 0 = gamma, 1 = gather.  Bytes are
+  // Profiling of finest-grid kernels: kind 0 = gamma, 1 = gather, 2 = fused
+  // three-axis operator.  Bytes are
   // algorithmic: every input element read once, every output written once.
   hipEvent_t pa = nullptr;
   bool prof(int l) const { return P->opt.profile && l == 0; }
@@ -430,7 +531,11 @@ struct Solver {
     (void)hipEventRecord(pb, st);
     const double p = sizeof(TV), K = P->K;
     double per;
-    if (kind == 0) per = (2 + K) * p;                       // u, c in; gamma out
+    if (kind == 2) {                                        // fused: no gamma round trip
+      if (mode == G_CHEB) per = (8 + K) * p;                // d, c, x, r, dinv in; x, r, d out
+      else if (mode == G_RESID) per = (6 + K) * p;          // u, c, b, dinv in; r, d out
+      else per = (2 + K) * p;                               // u, c in; y out
+    } else if (kind == 0) per = (2 + K) * p;                // u, c in; gamma out
     else if (mode == G_CHEB) per = (9 + K) * p;             // d, gamma, c, x, r, dinv in; x, r, d out
     else if (mode == G_RESID) per = (7 + K) * p;            // u, gamma, c, b, dinv in; r, d out
     else per = (3 + K) * p;                                 // u, gamma, c in; y out
@@ -442,6 +547,7 @@ struct Solver {
     HIPCHK(hipStreamSynchronize(st));
     std::snprintf(P->kst[0].name, 32, "gamma");
     std::snprintf(P->kst[1].name, 32, "gather");
+    std::snprintf(P->kst[2].name, 32, "apply3");
     for (auto& k : P->kst) { k.launches = 0; k.ms = 0; k.bytes = 0; }
     for (auto& r : P->recs) {
       float ms = 0;
@@ -454,16 +560,52 @@ struct Solver {
     P->pool_used = 0;
   }
 
-  // y = S u on level l for the instances of table t.
-  void apply(int l, const Table& t, TV* u, TV* out, int mode, double* partial) {
+  // Fused three-axis operator for table t of level l, or null when the
+  // two-pass kernels must be used (other shapes, FP64, option off).
+  const FTab* fused(int l, const Table& t) {
+    if constexpr (!(std::is_same<TV, float>::value && std::is_same<TC, float>::value)) {
+      return nullptr;
+    } else {
+      if (!P->opt.fused) return nullptr;
+      Level& L = P->lv[l];
+      const FTab* f = (&t == &L.all) ? &L.fall : (&t == &L.smooth) ? &L.fsmooth : nullptr;
+      return (f && f->ok) ? f : nullptr;
+    }
+  }
+
+  // One operator pass y = S u over table t with the epilogue of `mode`
+  // (GatherMode; vectors as for launch_gather).
+  void op(int l, const Table& t, TV* u, int mode, TV* out, const TV* b, TV* x, TV* r, TV* d, int cheb_step,
+          double* partial) {
     Level& L = P->lv[l];
+    if (const FTab* f = fused(l, t)) {
+      if constexpr (std::is_same<TV, float>::value && std::is_same<TC, float>::value) {
+        pbeg(l);
+        launch_apply3<float, float, float>(st, f->d, f->nb(), f->g, L.d, P->ci, u, C(L.coef), mode, out, b, x, r, d,
+                                           V(L.dinv), cheb_step, partial);
+        pend(l, 2, t, mode);
+      }
+      return;
+    }
     pbeg(l);
     launch_gamma<TV, TV, TC>(D, st, t.d, t.nb(), L.d, P->ci, u, C(L.coef), C(P->f), 0, V(L.gam));
     pend(l, 0, t, 0);
     pbeg(l);
-    launch_gather<TV, TV, TC>(D, st, t.d, t.nb(), L.d, P->ci, u, V(L.gam), C(L.coef), C(P->w), 0, mode, out,
-                              nullptr, nullptr, nullptr, nullptr, nullptr, 0, partial);
+    launch_gather<TV, TV, TC>(D, st, t.d, t.nb(), L.d, P->ci, u, V(L.gam), C(L.coef), C(P->w), 0, mode, out, b, x,
+                              r, d, V(L.dinv), cheb_step, partial);
     pend(l, 1, t, mode);
+  }
+
+  // y = S u on level l for the instances of table t.
+  void apply(int l, const Table& t, TV* u, TV* out, int mode, double* partial) {
+    op(l, t, u, mode, out, nullptr, nullptr, nullptr, nullptr, 0, partial);
+  }
+
+  // out = S u and the per-instance dot products u.out into dots[B].
+  void apply_dot(int l, const Table& t, TV* u, TV* out, double* dots) {
+    op(l, t, u, G_STORE_DOT, out, nullptr, nullptr, nullptr, nullptr, 0, P->partial);
+    const FTab* f = fused(l, t);
+    launch_finish_sum(st, P->partial, f ? f->d_bstart : t.d_bstart, P->B, dots);
   }
 
   // nu Chebyshev steps; the search direction is double-buffered (dd / dd2):
@@ -471,17 +613,10 @@ struct Solver {
   // the other buffer.  The start direction is in dd.
   void chebyshev(int l, TV* x, int nu) {
     Level& L = P->lv[l];
-    const Table& t = L.smooth;
     for (int s = 0; s < nu; ++s) {
       TV* cur = V((s & 1) ? L.dd2 : L.dd);
       TV* nxt = V((s & 1) ? L.dd : L.dd2);
-      pbeg(l);
-      launch_gamma<TV, TV, TC>(D, st, t.d, t.nb(), L.d, P->ci, cur, C(L.coef), C(P->f), 0, V(L.gam));
-      pend(l, 0, t, 0);
-      pbeg(l);
-      launch_gather<TV, TV, TC>(D, st, t.d, t.nb(), L.d, P->ci, cur, V(L.gam), C(L.coef), C(P->w), 0, G_CHEB,
-                                nullptr, nullptr, x, V(L.r), nxt, V(L.dinv), s, nullptr);
-      pend(l, 1, t, G_CHEB);
+      op(l, L.smooth, cur, G_CHEB, nullptr, nullptr, x, V(L.r), nxt, s, nullptr);
     }
   }
 
@@ -491,6 +626,8 @@ struct Solver {
     const int nu = P->opt.nu;
     if (!L.cinst64.empty())
       launch_bb_solve64<TV>(st, (int)L.cinst64.size(), L.d_cinst64, L.d, V(P->Sinv), b, x);
+    if (!L.cinst16.empty())
+      launch_bb_solve16<TV>(st, (int)L.cinst16.size(), L.d_cinst16, L.d, V(P->Sinv), b, x);
     if (!L.cinstg.empty()) launch_bb_solve<TV>(st, (int)L.cinstg.size(), L.d_cinstg, L.d, V(P->Sinv), b, x);
     if (L.smooth.nb() == 0) return;
     const Table& t = L.smooth;
@@ -501,13 +638,7 @@ struct Solver {
     if (use_net && P->net && l + 1 == P->net_level) learned(l + 1, V(Cc.b), V(Cc.x));
     else vcycle(l + 1, V(Cc.b), V(Cc.x));
     launch_prolong_add<TV>(D, st, t.d, t.nb(), L.d, Cc.d, V(Cc.x), x);
-    pbeg(l);
-    launch_gamma<TV, TV, TC>(D, st, t.d, t.nb(), L.d, P->ci, x, C(L.coef), C(P->f), 0, V(L.gam));
-    pend(l, 0, t, 0);
-    pbeg(l);
-    launch_gather<TV, TV, TC>(D, st, t.d, t.nb(), L.d, P->ci, x, V(L.gam), C(L.coef), C(P->w), 0, G_RESID, V(L.r),
-                              b, nullptr, nullptr, V(L.dd), V(L.dinv), 0, nullptr);
-    pend(l, 1, t, G_RESID);
+    op(l, t, x, G_RESID, V(L.r), b, nullptr, nullptr, V(L.dd), 0, nullptr);
     chebyshev(l, x, nu);
   }
 
@@ -522,8 +653,7 @@ struct Solver {
     launch_pcg_scalars(st, 0, B, first, tol2, P->rz_new, P->rz, P->beta, P->pq, P->alpha, P->rn2, P->r0n2,
                        P->active, P->iters);
     launch_update_p<TV>(st, t.d, t.nb(), L0.d, P->beta, V(P->zk), V(P->pk));
-    apply(0, t, V(P->pk), V(P->qk), G_STORE_DOT, P->partial);
-    finish(t, P->pq);
+    apply_dot(0, t, V(P->pk), V(P->qk), P->pq);
     launch_pcg_scalars(st, 1, B, 0, tol2, P->rz_new, P->rz, P->beta, P->pq, P->alpha, P->rn2, P->r0n2, P->active,
                        P->iters);
     launch_update_xr<TV>(st, t.d, t.nb(), L0.d, P->alpha, V(P->pk), V(P->qk), V(P->e), V(P->rk), P->partial);
@@ -627,8 +757,7 @@ struct Solver {
       launch_pcg_scalars(st, 0, B, it == 0, tol2, P->rz_new, P->rz, P->beta, P->pq, P->alpha, P->rn2, P->r0n2,
                          P->active, P->iters);
       launch_update_p<TV>(st, t.d, t.nb(), L0.d, P->beta, V(P->zk), V(P->pk));
-      apply(0, t, V(P->pk), V(P->qk), G_STORE_DOT, P->partial);
-      finish(t, P->pq);
+      apply_dot(0, t, V(P->pk), V(P->qk), P->pq);
       launch_pcg_scalars(st, 1, B, 0, tol2, P->rz_new, P->rz, P->beta, P->pq, P->alpha, P->rn2, P->r0n2, P->active,
                          P->iters);
       launch_update_xr<TV>(st, t.d, t.nb(), L0.d, P->alpha, V(P->pk), V(P->qk), V(P->e), V(P->rk), P->partial);
@@ -748,8 +877,7 @@ struct Solver {
         launch_mul_dinv<TV>(st, t.d, t.nb(), L.d, V(L.dinv), V(L.r), V(L.x), P->partial);  // partial: x^T D x
       }
       finish(t, P->pq);
-      apply(l, t, V(L.x), V(L.r), G_STORE_DOT, P->partial);                                 // x^T S x
-      finish(t, P->rz);
+      apply_dot(l, t, V(L.x), V(L.r), P->rz);                                               // x^T S x
       std::vector<double> vsv(P->B), vdv(P->B);
       HIPCHK(hipMemcpyAsync(vsv.data(), P->rz, P->B * sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(hipMemcpyAsync(vdv.data(), P->pq, P->B * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -850,14 +978,19 @@ struct Solver {
     for (int l = 0; l < (int)P->lv.size(); ++l) {
       Level& L = P->lv[l];
       L.cinst64.clear();
+      L.cinst16.clear();
       L.cinstg.clear();
       for (int b = 0; b < B; ++b)
         if (L.h[b].N && L.h[b].coarsest) {
           L.h[b].doff = boff[b];
-          (mn[b] == 64 ? L.cinst64 : L.cinstg).push_back(b);
+          (mn[b] == 64 ? L.cinst64 : mn[b] <= 16 ? L.cinst16 : L.cinstg).push_back(b);
         }
-      if (!L.cinst64.empty() || !L.cinstg.empty())
+      if (!L.cinst64.empty() || !L.cinst16.empty() || !L.cinstg.empty())
         HIPCHK(hipMemcpyAsync(L.d, L.h.data(), L.h.size() * sizeof(LInst), hipMemcpyHostToDevice, st));
+      if (!L.cinst16.empty()) {
+        L.d_cinst16 = P->alloc<int>(L.cinst16.size());
+        HIPCHK(hipMemcpyAsync(L.d_cinst16, L.cinst16.data(), L.cinst16.size() * sizeof(int), hipMemcpyHostToDevice, st));
+      }
       if (!L.cinst64.empty()) {
         L.d_cinst64 = P->alloc<int>(L.cinst64.size());
         HIPCHK(hipMemcpyAsync(L.d_cinst64, L.cinst64.data(), L.cinst64.size() * sizeof(int), hipMemcpyHostToDevice, st));
@@ -1077,6 +1210,8 @@ void build_impl(mpde_problem* P, const mpde_desc* d) {
     make_table(L.all, L.h, B, sel_all);
     make_table(L.smooth, L.h, B, sel_smooth);
     make_table(L.dense, L.h, B, sel_dense);
+    make_ftab(L.fall, L.h, B, sel_all, D);
+    make_ftab(L.fsmooth, L.h, B, sel_smooth, D);
   }
   // device structures
   size_t maxnb = 1;
@@ -1084,7 +1219,9 @@ void build_impl(mpde_problem* P, const mpde_desc* d) {
     L.d = P->alloc<LInst>(B);
     HIPCHK(hipMemcpy(L.d, L.h.data(), B * sizeof(LInst), hipMemcpyHostToDevice));
     upload_table(P, L.all); upload_table(P, L.smooth); upload_table(P, L.dense);
+    upload_ftab(P, L.fall); upload_ftab(P, L.fsmooth);
     maxnb = std::max(maxnb, L.all.h.size());
+    maxnb = std::max(maxnb, (size_t)L.fall.bstart.back());
   }
   S.alloc_vectors();
   const long long n0 = P->lv[0].npts;
@@ -1181,6 +1318,7 @@ int mpde_default_options(mpde_options* o) {
   o->check_every = 2;
   o->max_levels = 16;
   o->graph = 1;
+  o->fused = 1;
   return MPDE_OK;
 }
 
@@ -1492,9 +1630,9 @@ int mpde_autotune(mpde_problem* p, void* z, int32_t* chosen, double* best_ms) {
 
 int mpde_kernel_stats(const mpde_problem* p, mpde_kstat* out, int32_t max) {
   if (!p || !p->opt.profile) return 0;
-  for (int i = 0; i < 2 && i < max; ++i)
+  for (int i = 0; i < 3 && i < max; ++i)
     if (out) out[i] = p->kst[i];
-  return 2;
+  return 3;
 }
 
 int mpde_levels(const mpde_problem* p, int32_t b, int32_t* shapes) {

@@ -1,0 +1,450 @@
+// Fused matrix-free operator for levels with three axes (t, x, y), t not
+// periodic: y = A_u^T Pi (A_u u - sigma d) with the epilogues of GatherMode,
+// in one pass that evaluates every constraint row once.
+//
+// The two-pass kernels (k_gamma, k_gather) re-evaluate the rows of each
+// neighbour in every point that gathers from it (five times per axis) and
+// move gamma through HBM.  Here a block owns an (x, y) tile of one instance
+// and marches over the time planes.  At plane p it evaluates, for the tile
+// and a halo of two points (four next to a non-periodic edge), the rows of
+// all three axes (Eqs. 5-7), the coupling scalar gamma and the projected row
+// residuals of the reduced operator (the header of mpde_internal.hpp gives
+// the formulation).  Then:
+//   * the projected x and y rows go to LDS; after a barrier each tile point
+//     gathers the rows whose stencils contain it;
+//   * the projected time rows are scattered into a per-thread register ring
+//     of partial results for the planes p-4 .. p+4 (the thread owns the same
+//     (x, y) point on every plane, so no other thread touches that ring);
+//   * plane p-2 then has every contribution (rows at most two planes above
+//     it reach it, except the one-sided rows of the last five planes, which
+//     are finished after the last plane) and its epilogue runs.
+// u is staged plane by plane in LDS (double-buffered, the next plane loaded
+// into registers while the current one is processed), and the time window
+// of every owned point is a register ring, so each value of u, of the
+// coefficients and of the mode vectors crosses HBM once per tile.
+#include "mpde_fused.hpp"
+
+#include <type_traits>
+
+namespace mpde {
+
+// Compile-time 5-point weights for a window position known at compile time:
+// derivatives at 0 of the Lagrange basis polynomials on the nodes m - wp,
+// m = 0..4 (the same moment conditions of Eq. 5 that the host table solves;
+// here in closed form so that the weights become instruction literals).
+__host__ __device__ constexpr double lag_d1(int wp, int k) {
+  double den = 1, s = 0;
+  for (int m = 0; m < 5; ++m)
+    if (m != k) den *= (double)(k - m);
+  for (int j = 0; j < 5; ++j) {
+    if (j == k) continue;
+    double pr = 1;
+    for (int m = 0; m < 5; ++m)
+      if (m != k && m != j) pr *= -(double)(m - wp);
+    s += pr;
+  }
+  return s / den;
+}
+__host__ __device__ constexpr double lag_d2(int wp, int k) {
+  double den = 1, s = 0;
+  for (int m = 0; m < 5; ++m)
+    if (m != k) den *= (double)(k - m);
+  for (int j = 0; j < 5; ++j) {
+    if (j == k) continue;
+    for (int l = 0; l < 5; ++l) {
+      if (l == k || l == j) continue;
+      double pr = 1;
+      for (int m = 0; m < 5; ++m)
+        if (m != k && m != j && m != l) pr *= -(double)(m - wp);
+      s += pr;
+    }
+  }
+  return s / den;
+}
+template <typename TA, int WP, int K> __device__ __forceinline__ constexpr TA CW1() { return (TA)lag_d1(WP, K); }
+template <typename TA, int WP, int K> __device__ __forceinline__ constexpr TA CW2() { return (TA)lag_d2(WP, K); }
+static_assert(lag_d1(2, 0) * 12 == 1 && lag_d1(2, 1) * 12 == -8 && lag_d1(2, 3) * 12 == 8, "5-point weights");
+static_assert(lag_d2(2, 2) * 12 == -30 && lag_d2(0, 0) * 12 == 35 && lag_d1(0, 0) * 12 == -25, "5-point weights");
+
+constexpr int kFMaxU = 2;   // staged u values per thread and plane
+
+__device__ __forceinline__ int fwrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// Difference sums of the time window of a point at window position WP; the
+// ring tu holds the planes p-4 .. p+4, so the window starts at 4 - WP.
+template <typename TA, int WP>
+__device__ __forceinline__ void t_sums(const TA* tu, TA& s1, TA& s2) {
+  s1 = CW1<TA, WP, 0>() * tu[4 - WP] + CW1<TA, WP, 1>() * tu[5 - WP] + CW1<TA, WP, 2>() * tu[6 - WP] +
+       CW1<TA, WP, 3>() * tu[7 - WP] + CW1<TA, WP, 4>() * tu[8 - WP];
+  s2 = CW2<TA, WP, 0>() * tu[4 - WP] + CW2<TA, WP, 1>() * tu[5 - WP] + CW2<TA, WP, 2>() * tu[6 - WP] +
+       CW2<TA, WP, 3>() * tu[7 - WP] + CW2<TA, WP, 4>() * tu[8 - WP];
+}
+// Scatter of a time row's projected difference residuals (already weighted
+// by wC1, wC2) into the partial results of the planes of its window.
+template <typename TA, int WP>
+__device__ __forceinline__ void t_push(TA* acc, TA q1, TA q2) {
+  acc[4 - WP] -= CW1<TA, WP, 0>() * q1 + CW2<TA, WP, 0>() * q2;
+  acc[5 - WP] -= CW1<TA, WP, 1>() * q1 + CW2<TA, WP, 1>() * q2;
+  acc[6 - WP] -= CW1<TA, WP, 2>() * q1 + CW2<TA, WP, 2>() * q2;
+  acc[7 - WP] -= CW1<TA, WP, 3>() * q1 + CW2<TA, WP, 3>() * q2;
+  acc[8 - WP] -= CW1<TA, WP, 4>() * q1 + CW2<TA, WP, 4>() * q2;
+}
+// Rows of a periodic axis (x or y) at a point from the staged u plane: window
+// sums and Taylor residuals; `w0` is the LDS address of the window start (the
+// point itself is at w0 + 2 sd), `sd` the LDS stride along the axis.
+template <typename TA>
+__device__ __forceinline__ void xy_rows(const TA* su, int w0, int sd, TA ui, TA wT, TA wC1, TA wC2, TA& rTp,
+                                        TA& rTm, TA& rC1, TA& rC2) {
+  const TA w0v = su[w0], w1v = su[w0 + sd], w3v = su[w0 + 3 * sd], w4v = su[w0 + 4 * sd];
+  const TA s1 = CW1<TA, 2, 0>() * w0v + CW1<TA, 2, 1>() * w1v + CW1<TA, 2, 3>() * w3v + CW1<TA, 2, 4>() * w4v;
+  const TA s2 = CW2<TA, 2, 0>() * w0v + CW2<TA, 2, 1>() * w1v + CW2<TA, 2, 2>() * ui + CW2<TA, 2, 3>() * w3v +
+                CW2<TA, 2, 4>() * w4v;
+  rTp = wT * (ui - w3v);
+  rTm = wT * (ui - w1v);
+  rC1 = -wC1 * s1;
+  rC2 = -wC2 * s2;
+}
+
+// Gather of the projected rows of a periodic axis staged in LDS into the
+// result at a tile point: q1/q2/qp/qm are the four row-value planes (already
+// weighted), `a` the point's slot, `sd` the slot stride along the axis.  Row
+// j + o contains j at window slot 2 - o; T+ of j - 1 and T- of j + 1 end at j.
+template <typename TA>
+__device__ __forceinline__ TA xy_gather(const TA* q1, const TA* q2, const TA* qp, const TA* qm, int a, int sd) {
+  TA y = qp[a] + qm[a] - qp[a - sd] - qm[a + sd];
+  y -= CW1<TA, 2, 4>() * q1[a - 2 * sd] + CW2<TA, 2, 4>() * q2[a - 2 * sd];
+  y -= CW1<TA, 2, 3>() * q1[a - sd] + CW2<TA, 2, 3>() * q2[a - sd];
+  y -= CW2<TA, 2, 2>() * q2[a];
+  y -= CW1<TA, 2, 1>() * q1[a + sd] + CW2<TA, 2, 1>() * q2[a + sd];
+  y -= CW1<TA, 2, 0>() * q1[a + 2 * sd] + CW2<TA, 2, 0>() * q2[a + 2 * sd];
+  return y;
+}
+
+template <typename TA>
+__device__ __forceinline__ double fblock_sum(double v) {
+  __shared__ double part[kFThreads / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) part[wid] = v;
+  __syncthreads();
+  double s = 0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 0; w < kFThreads / 64; ++w) s += part[w];
+  }
+  return s;
+}
+
+template <typename TA, typename TV, typename TC, int MODE>
+__global__ void __launch_bounds__(kFThreads) k_apply3(const FTile* __restrict__ tiles, FGeom g,
+                                                      const LInst* __restrict__ li, CIdx ci,
+                                                      const TV* __restrict__ u, const TC* __restrict__ c,
+                                                      TV* __restrict__ out, const TV* __restrict__ bvec,
+                                                      TV* __restrict__ xv, TV* __restrict__ rv,
+                                                      TV* __restrict__ dv, const TV* __restrict__ dinv,
+                                                      int cheb_step, double* __restrict__ partial) {
+  extern __shared__ __align__(16) unsigned char fsm[];
+  TA* su = reinterpret_cast<TA*>(fsm);     // [2][uplane] staged u planes
+  TA* sq = su + 2 * g.uplane;              // [2][8][qplane] projected x rows (0-3), y rows (4-7)
+  const FTile tl = tiles[blockIdx.x];
+  const LInst& L = li[tl.inst];
+  const int nt = L.n[0], nx = L.n[1], ny = L.n[2];
+  const FSpan X = fspan(tl.x0, g.TX, nx, 1);
+  const FSpan Y = fspan(tl.y0, g.TY, ny, 1);
+  const int stt = L.str[0], stx = L.str[1], sty = L.str[2];   // an instance level has < 2^31 points
+  const TV* U = u + L.voff;
+  const TC* Cf = c + L.coff;
+  const int tid = threadIdx.x;
+
+  // ---- the row point owned by this thread (the same (x, y) on every plane)
+  const bool act = tid < X.qn * Y.qn;
+  const int lx = act ? tid / Y.qn : 0, ly = act ? tid - lx * Y.qn : 0;
+  const int gx = fwrap(X.qlo + lx, nx), gy = fwrap(Y.qlo + ly, ny);
+  const int gof = gx * stx + gy * sty;
+  // staged u: the point sits at (lx + 2, ly + 2); its windows start 2 before
+  const int axw = lx * Y.un + (ly + 2);
+  const int ayw = (lx + 2) * Y.un + ly;
+  const int sx = lx + X.qoff, sy = ly + Y.qoff;
+  const int qsl = sx * Y.qs + sy;
+  int qdx = -1, qdy = -1;   // wrapped copies of a whole-axis tile
+  if (X.fw) {
+    if (lx < 2) qdx = (sx + nx) * Y.qs + sy;
+    else if (lx >= nx - 2) qdx = (sx - nx) * Y.qs + sy;
+  }
+  if (Y.fw) {
+    if (ly < 2) qdy = qsl + ny;
+    else if (ly >= ny - 2) qdy = qsl - ny;
+  }
+  const bool tile = act && (unsigned)(lx - X.ilo) < (unsigned)X.icnt && (unsigned)(ly - Y.ilo) < (unsigned)Y.icnt;
+
+  // ---- rings: tu[k] = u at plane p - 4 + k of the owned point; acc likewise
+  TA tu[9], acc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const int pl = k - 4;
+    tu[k] = (act && pl >= 0 && pl < nt) ? (TA)U[pl * stt + gof] : (TA)0;
+    acc[k] = 0;
+  }
+  // staged-u slot -> offset within a plane (fixed over the planes)
+  const int nus = X.un * Y.un;
+  int uof[kFMaxU];
+#pragma unroll
+  for (int k = 0; k < kFMaxU; ++k) {
+    const int i = tid + k * kFThreads;
+    uof[k] = -1;
+    if (i < nus) {
+      const int ux = i / Y.un, uy = i - ux * Y.un;
+      uof[k] = fwrap(X.ulo + ux, nx) * stx + fwrap(Y.ulo + uy, ny) * sty;
+    }
+  }
+  // coefficient planes of c_phi and of the first / second derivative of
+  // each axis (null: no such field)
+  const TC* cpl[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) cpl[k] = ci.k[k] >= 0 ? Cf + (long long)ci.k[k] * L.N : nullptr;
+
+  // Loads run two planes ahead of their use, into register sets indexed by
+  // plane parity; the plane loop is unrolled by two so that every set has a
+  // fixed register name (a register copy would wait for the load):
+  //   cs[q]  coefficients of the next plane of parity q to be processed,
+  //   us[q]  u of the next plane of parity q to be staged in LDS,
+  //   ts[q]  the next time-ring entry of parity q.
+  TA cs[2][7], us[2][kFMaxU], ts[2];
+  auto ld_coef = [&](int pl, TA(&d)[7]) {
+#pragma unroll
+    for (int k = 0; k < 7; ++k) d[k] = (act && cpl[k] && pl < nt) ? (TA)cpl[k][pl * stt + gof] : (TA)0;
+  };
+  auto ld_u = [&](int pl, TA(&d)[kFMaxU]) {
+#pragma unroll
+    for (int k = 0; k < kFMaxU; ++k) d[k] = (uof[k] >= 0 && pl < nt) ? (TA)U[pl * stt + uof[k]] : (TA)0;
+  };
+  auto ld_t = [&](int pl) -> TA { return (act && pl < nt) ? (TA)U[pl * stt + gof] : (TA)0; };
+#pragma unroll
+  for (int k = 0; k < kFMaxU; ++k)
+    if (uof[k] >= 0) su[tid + k * kFThreads] = (TA)U[uof[k]];
+  ld_coef(0, cs[0]);
+  ld_coef(1, cs[1]);
+  ld_u(1, us[1]);
+  ld_u(2, us[0]);
+  ts[1] = ld_t(5);
+  ts[0] = ld_t(6);
+  __syncthreads();
+
+  const TA wT0 = (TA)L.wT[0], wC10 = (TA)L.wC1[0], wC20 = (TA)L.wC2[0];
+  const TA wTx = (TA)L.wT[1], wC1x = (TA)L.wC1[1], wC2x = (TA)L.wC2[1];
+  const TA wTy = (TA)L.wT[2], wC1y = (TA)L.wC1[2], wC2y = (TA)L.wC2[2];
+  const TA s1t = (TA)L.is1[0], s2t = (TA)L.is2[0], s1x = (TA)L.is1[1], s2x = (TA)L.is2[1];
+  const TA s1y = (TA)L.is1[2], s2y = (TA)L.is2[2];
+  const TA gx11 = (TA)L.gi[1][0][0], gx12 = (TA)L.gi[1][0][1], gx22 = (TA)L.gi[1][0][2];
+  const TA gy11 = (TA)L.gi[2][0][0], gy12 = (TA)L.gi[2][0][1], gy22 = (TA)L.gi[2][0][2];
+
+  // Chebyshev coefficients of this step (uniform)
+  TA chA = 0, chB = 0;
+  if (MODE == G_CHEB) {
+    const double th = L.cheb_theta, de = L.cheb_delta, s1 = th / de;
+    double rp = 1.0 / s1, rn = 0;
+    for (int s = 0; s <= cheb_step; ++s) { rn = 1.0 / (2.0 * s1 - rp); if (s < cheb_step) rp = rn; }
+    chA = (TA)(rn * rp);
+    chB = (TA)(2.0 * rn / de);
+  }
+  const TA ith = (TA)(1.0 / L.cheb_theta);
+  double dot = 0;
+
+  auto finalize = [&](int j, TA y, TA uj) {
+    const long long gj = L.voff + j * stt + gof;
+    if (MODE == G_STORE) {
+      out[gj] = (TV)y;
+    } else if (MODE == G_STORE_DOT) {
+      out[gj] = (TV)y;
+      dot += (double)uj * (double)y;
+    } else if (MODE == G_RESID) {
+      const TA r = (bvec ? (TA)bvec[gj] : (TA)0) - y;
+      out[gj] = (TV)r;
+      if (dv) dv[gj] = (TV)((TA)dinv[gj] * r * ith);
+    } else {   // G_CHEB
+      xv[gj] = (TV)((TA)xv[gj] + uj);
+      const TA r = (TA)rv[gj] - y;
+      rv[gj] = (TV)r;
+      dv[gj] = (TV)(chA * uj + chB * (TA)dinv[gj] * r);
+    }
+  };
+
+  // One plane.  Phase A evaluates the rows at plane p (staged u slot p & 1)
+  // and stores the projected x and y rows in row buffer p & 1, then stages
+  // plane p + 1; after the single barrier, phase B gathers plane p.  Buffers
+  // alternate, so the next phase A (which writes the other buffers) needs no
+  // second barrier: everything it overwrites was last read before this one.
+  // WP is the window position of plane p on the time axis (0, 1 on the
+  // first two planes, 3, 4 on the last two, 2 elsewhere), a template
+  // constant so that every ring index is fixed at compile time.
+  auto step = [&](int p, auto par, auto wpc) {
+    constexpr int Q = decltype(par)::value;   // p & 1
+    constexpr int WP = decltype(wpc)::value;
+    constexpr int tpt = WP != 4, tmt = WP != 0;
+    constexpr int clt = tmt ? (tpt ? 0 : 2) : 1;
+    const TA* cu = su + Q * g.uplane;
+    TA* nu = su + (1 - Q) * g.uplane;
+    TA* qb = sq + Q * 8 * g.qplane;
+    TA* q1x = qb;
+    TA* q2x = qb + g.qplane;
+    TA* qpx = qb + 2 * g.qplane;
+    TA* qmx = qb + 3 * g.qplane;
+    TA* q1y = qb + 4 * g.qplane;
+    TA* q2y = qb + 5 * g.qplane;
+    TA* qpy = qb + 6 * g.qplane;
+    TA* qmy = qb + 7 * g.qplane;
+    const TA gt11 = (TA)L.gi[0][clt][0], gt12 = (TA)L.gi[0][clt][1], gt22 = (TA)L.gi[0][clt][2];
+    const bool onB = (L.dlo[0] && p == 0) || (L.dhi[0] && p == nt - 1);
+
+    if (act) {
+      const TA* cc = cs[Q];
+      const TA ui = tu[4];
+      // time rows
+      TA a1, a2;
+      t_sums<TA, WP>(tu, a1, a2);
+      const TA rTpt = tpt ? wT0 * (ui - tu[5]) : (TA)0;
+      const TA rTmt = tmt ? wT0 * (ui - tu[3]) : (TA)0;
+      const TA rC1t = -wC10 * a1, rC2t = -wC20 * a2;
+      // x and y rows
+      TA rTpx, rTmx, rC1x, rC2x, rTpy, rTmy, rC1y, rC2y;
+      xy_rows<TA>(cu, axw, Y.un, ui, wTx, wC1x, wC2x, rTpx, rTmx, rC1x, rC2x);
+      xy_rows<TA>(cu, ayw, 1, ui, wTy, wC1y, wC2y, rTpy, rTmy, rC1y, rC2y);
+      // Sherman-Morrison scalar gamma
+      const TA c0 = cc[0];
+      const TA cat = cc[1] * s1t, catt = cc[2] * s2t;
+      const TA cax = cc[3] * s1x, caxx = cc[4] * s2x;
+      const TA cay = cc[5] * s1y, cayy = cc[6] * s2y;
+      const TA b1t = wT0 * (rTpt - rTmt) + wC10 * rC1t, b2t = wT0 * (rTpt + rTmt) * (TA)0.5 + wC20 * rC2t;
+      const TA b1x = wTx * (rTpx - rTmx) + wC1x * rC1x, b2x = wTx * (rTpx + rTmx) * (TA)0.5 + wC2x * rC2x;
+      const TA b1y = wTy * (rTpy - rTmy) + wC1y * rC1y, b2y = wTy * (rTpy + rTmy) * (TA)0.5 + wC2y * rC2y;
+      TA num = c0 * ui;
+      TA kap = 1;
+      {
+        const TA g1 = gt11 * b1t + gt12 * b2t, g2 = gt12 * b1t + gt22 * b2t;
+        const TA h1 = gt11 * cat + gt12 * catt, h2 = gt12 * cat + gt22 * catt;
+        kap += cat * h1 + catt * h2;
+        num -= cat * g1 + catt * g2;
+      }
+      {
+        const TA g1 = gx11 * b1x + gx12 * b2x, g2 = gx12 * b1x + gx22 * b2x;
+        const TA h1 = gx11 * cax + gx12 * caxx, h2 = gx12 * cax + gx22 * caxx;
+        kap += cax * h1 + caxx * h2;
+        num -= cax * g1 + caxx * g2;
+      }
+      {
+        const TA g1 = gy11 * b1y + gy12 * b2y, g2 = gy12 * b1y + gy22 * b2y;
+        const TA h1 = gy11 * cay + gy12 * cayy, h2 = gy12 * cay + gy22 * cayy;
+        kap += cay * h1 + cayy * h2;
+        num -= cay * g1 + cayy * g2;
+      }
+      const TA gam = num / kap;
+      // projected rows: the eliminated derivative unknowns x1, x2 of each
+      // axis, then the residuals of its rows, weighted for the gather
+      {
+        const TA e1 = b1x + cax * gam, e2 = b2x + caxx * gam;
+        const TA x1 = -(gx11 * e1 + gx12 * e2), x2 = -(gx12 * e1 + gx22 * e2);
+        const TA Q1 = wC1x * (rC1x + wC1x * x1), Q2 = wC2x * (rC2x + wC2x * x2);
+        const TA Tp = wTx * (rTpx + wTx * (x1 + (TA)0.5 * x2));
+        const TA Tm = wTx * (rTmx + wTx * (-x1 + (TA)0.5 * x2));
+        q1x[qsl] = Q1; q2x[qsl] = Q2; qpx[qsl] = Tp; qmx[qsl] = Tm;
+        if (qdx >= 0) { q1x[qdx] = Q1; q2x[qdx] = Q2; qpx[qdx] = Tp; qmx[qdx] = Tm; }
+      }
+      {
+        const TA e1 = b1y + cay * gam, e2 = b2y + cayy * gam;
+        const TA x1 = -(gy11 * e1 + gy12 * e2), x2 = -(gy12 * e1 + gy22 * e2);
+        const TA Q1 = wC1y * (rC1y + wC1y * x1), Q2 = wC2y * (rC2y + wC2y * x2);
+        const TA Tp = wTy * (rTpy + wTy * (x1 + (TA)0.5 * x2));
+        const TA Tm = wTy * (rTmy + wTy * (-x1 + (TA)0.5 * x2));
+        q1y[qsl] = Q1; q2y[qsl] = Q2; qpy[qsl] = Tp; qmy[qsl] = Tm;
+        if (qdy >= 0) { q1y[qdy] = Q1; q2y[qdy] = Q2; qpy[qdy] = Tp; qmy[qdy] = Tm; }
+      }
+      if (tile) {
+        const TA e1 = b1t + cat * gam, e2 = b2t + catt * gam;
+        const TA x1 = -(gt11 * e1 + gt12 * e2), x2 = -(gt12 * e1 + gt22 * e2);
+        const TA Q1 = wC10 * (rC1t + wC10 * x1), Q2 = wC20 * (rC2t + wC20 * x2);
+        const TA Tp = tpt ? wT0 * (rTpt + wT0 * (x1 + (TA)0.5 * x2)) : (TA)0;
+        const TA Tm = tmt ? wT0 * (rTmt + wT0 * (-x1 + (TA)0.5 * x2)) : (TA)0;
+        TA e = c0 * gam + Tp + Tm;                     // equation row (q_E = gamma), own Taylor rows
+        if (onB) e += ui;                              // boundary row
+        acc[4] += e;
+        acc[5] -= Tp;                                  // T+ of plane p ends at p + 1
+        acc[3] -= Tm;                                  // T- of plane p ends at p - 1
+        t_push<TA, WP>(acc, Q1, Q2);
+      }
+    }
+    ld_coef(p + 2, cs[Q]);
+    if (p + 1 < nt) {
+#pragma unroll
+      for (int k = 0; k < kFMaxU; ++k)
+        if (uof[k] >= 0) nu[tid + k * kFThreads] = us[1 - Q][k];
+    }
+    ld_u(p + 3, us[1 - Q]);
+    __syncthreads();
+    if (tile) {
+      acc[4] += xy_gather<TA>(q1x, q2x, qpx, qmx, qsl, Y.qs) + xy_gather<TA>(q1y, q2y, qpy, qmy, qsl, 1);
+      // plane p - 2 is complete unless it is one of the last five planes
+      if (p >= 2 && p - 2 < nt - 5) finalize(p - 2, acc[2], tu[2]);
+      if (WP == 4) {   // p = nt - 1
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+          const int j = p - 4 + k;
+          if (j >= 0 && j >= nt - 5) finalize(j, acc[k], tu[k]);
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) { tu[k] = tu[k + 1]; acc[k] = acc[k + 1]; }
+    tu[8] = ts[1 - Q];
+    acc[8] = 0;
+    ts[1 - Q] = ld_t(p + 7);
+  };
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  using I3 = std::integral_constant<int, 3>;
+  using I4 = std::integral_constant<int, 4>;
+  step(0, I0(), I0());
+  step(1, I1(), I1());
+  int p = 2;
+  for (; p + 1 <= nt - 3; p += 2) {
+    step(p, I0(), I2());
+    step(p + 1, I1(), I2());
+  }
+  if (p <= nt - 3) step(p++, I0(), I2());
+  if (p & 1) {
+    step(p, I1(), I3());
+    step(p + 1, I0(), I4());
+  } else {
+    step(p, I0(), I3());
+    step(p + 1, I1(), I4());
+  }
+  if (MODE == G_STORE_DOT) {
+    const double sdot = fblock_sum<TA>(dot);
+    if (threadIdx.x == 0) partial[tl.pad] = sdot;
+  }
+}
+
+template <typename TA, typename TV, typename TC>
+void launch_apply3(hipStream_t st, const FTile* tiles, int nb, FGeom g, const LInst* li, CIdx ci, const TV* u,
+                   const TC* c, int mode, TV* out, const TV* bvec, TV* x, TV* r, TV* d, const TV* dinv,
+                   int cheb_step, double* partial) {
+  if (nb <= 0) return;
+  const size_t lds = sizeof(TA) * (2 * (size_t)g.uplane + 16 * (size_t)g.qplane);
+#define MPDE_APPLY3(M)                                                                                          \
+  hipLaunchKernelGGL((k_apply3<TA, TV, TC, M>), dim3((unsigned)nb), dim3(kFThreads), lds, st, tiles, g, li, ci, u, \
+                     c, out, bvec, x, r, d, dinv, cheb_step, partial)
+  switch (mode) {
+    case G_STORE: MPDE_APPLY3(G_STORE); break;
+    case G_RESID: MPDE_APPLY3(G_RESID); break;
+    case G_CHEB: MPDE_APPLY3(G_CHEB); break;
+    default: MPDE_APPLY3(G_STORE_DOT); break;
+  }
+#undef MPDE_APPLY3
+}
+
+template void launch_apply3<float, float, float>(hipStream_t, const FTile*, int, FGeom, const LInst*, CIdx,
+                                                 const float*, const float*, int, float*, const float*, float*,
+                                                 float*, float*, const float*, int, double*);
+
+}  // namespace mpde

@@ -1,0 +1,77 @@
+// Fused operator for three-axis levels (t, x, y): tile geometry shared by the
+// host (tile tables, LDS sizing) and the kernel, and the launch wrapper.
+#pragma once
+#include "mpde_internal.hpp"
+
+namespace mpde {
+
+constexpr int kFThreads = 768;   // threads per block
+constexpr int kFMaxQ = 1;        // row points per thread and plane
+
+// One block: an instance and the origin of its (x, y) tile; the block marches
+// over every time plane.
+struct FTile {
+  int inst, x0, y0, pad;
+};
+
+// Per-launch constants: tile extents and LDS strides (maxima over the tiles).
+struct FGeom {
+  int TX, TY;        // tile extent in x and y
+  int uplane;        // elements of one staged u plane
+  int qplane;        // elements of one staged row-value plane
+};
+
+// Ranges of one axis for a tile [x0, x0 + T) of an axis with n points:
+//   rows  [qlo, qlo + qn): points whose rows reach the tile (windows and
+//                          Taylor neighbours);
+//   u     [ulo, ulo + un): points those rows read;
+//   slots: staged row values are stored at (row - qlo) + qoff, with qoff = 2
+//          and wrapped copies at both ends when the tile spans a whole
+//          periodic axis (fw), so that every read is a plain offset;
+//   tile  [ilo, ilo + icnt) in row-local coordinates.
+struct FSpan {
+  int qlo, qn, ulo, un, fw, qoff, qs, ilo, icnt;
+};
+
+__host__ __device__ inline int fclampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+__host__ __device__ inline FSpan fspan(int x0, int T, int n, int per) {
+  FSpan s;
+  const int x1 = (x0 + T < n) ? x0 + T : n;
+  s.icnt = x1 - x0;
+  if (per) {
+    s.fw = (x0 == 0 && x1 == n) ? 1 : 0;
+    s.qlo = s.fw ? 0 : x0 - 2;
+    s.qn = s.fw ? n : s.icnt + 4;
+    s.ulo = s.qlo - 2;
+    s.un = s.qn + 4;
+    s.qoff = s.fw ? 2 : 0;
+    s.qs = s.qn + (s.fw ? 4 : 0);
+    s.ilo = x0 - s.qlo;
+    return s;
+  }
+  // Rows 0..2 (window 0..4) reach points up to 4, rows n-3..n-1 reach down to
+  // n-5; other rows reach +-2.
+  const int qlo = x0 <= 4 ? 0 : x0 - 2;
+  const int qhi = x1 >= n - 4 ? n : x1 + 2;
+  const int ulo = fclampi(qlo - 2, 0, n - 5), uhi = fclampi(qhi - 3, 0, n - 5) + 5;
+  s.fw = 0;
+  s.qlo = qlo;
+  s.qn = qhi - qlo;
+  s.ulo = ulo;
+  s.un = uhi - ulo;
+  s.qoff = 0;
+  s.qs = s.qn;
+  s.ilo = x0 - qlo;
+  return s;
+}
+
+// y = S u (no right-hand-side terms) with the epilogue of `mode`
+// (GatherMode); every instance of the tile table must have periodic x and y
+// axes and a non-periodic time axis of at least five points.
+template <typename TA, typename TV, typename TC>
+void launch_apply3(hipStream_t st, const FTile* tiles, int nb, FGeom g, const LInst* li, CIdx ci, const TV* u,
+                   const TC* c, int mode, TV* out, const TV* bvec, TV* x, TV* r, TV* d, const TV* dinv,
+                   int cheb_step, double* partial);
+
+}  // namespace mpde

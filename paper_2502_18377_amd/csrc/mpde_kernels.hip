@@ -1505,6 +1505,127 @@ __global__ void __launch_bounds__(kBlock) k_bb_solve64(const int* __restrict__ i
   }
 }
 
+// Specialisation for planes of at most 16 points: one wavefront per
+// instance, lane (r, h) = row r, column class h (columns h, h+4, h+8, h+12).
+// The recurrence needs no barrier: row sums are lane shuffles, the
+// substituted values of the last four planes stay in registers, and the
+// band blocks of the next plane are loaded while the current one is reduced.
+constexpr int kBBS = 16;
+template <typename TV>
+__global__ void __launch_bounds__(64) k_bb_solve16(const int* __restrict__ inst_list, const LInst* __restrict__ li,
+                                                   const TV* __restrict__ Lb, const TV* __restrict__ bvec,
+                                                   TV* __restrict__ xvec) {
+  const LInst& L = li[inst_list[blockIdx.x]];
+  const int T = L.n[0], m = L.N / T;
+  const long long base = L.doff;
+  __shared__ double ys[2048];           // y then x (T * m <= 2048, the dense-solve limit)
+  const int lane = threadIdx.x, r = lane >> 2, h = lane & 3;
+  const bool live = r < m;
+  const TV* B = bvec + L.voff;
+  TV* X = xvec + L.voff;
+  auto rowsum = [](double v) {
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    return v;
+  };
+  // forward: y_t = Dinv_t (b_t - sum_k L[t][k] y_{t-k}); lane holds row r of
+  // L[t][k] at its columns and of Dinv_t
+  double yh[4][4] = {};                 // yh[k-1][j] = y_{t-k}[h + 4j]
+  double lc[5][4], ln[5][4];
+  auto load_fwd = [&](int t, double (&dst)[5][4]) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int c = h + 4 * j;
+        dst[k][j] = (live && c < m && k <= t && t < T) ? (double)Lb[bb_at(base, t, k, m) + (long long)r * m + c] : 0.0;
+      }
+  };
+  load_fwd(0, lc);
+  for (int t = 0; t < T; ++t) {
+    load_fwd(t + 1, ln);
+    double s = (live && h == 0) ? (double)B[(long long)t * m + r] : 0.0;
+#pragma unroll
+    for (int k = 1; k <= 4; ++k)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) s -= lc[k][j] * yh[k - 1][j];
+    s = rowsum(s);
+    double v = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = h + 4 * j;
+      const double sc = __shfl(s, (c < 16 ? c : 15) * 4, 64);
+      if (c <= r) v += lc[0][j] * sc;
+    }
+    const double y = rowsum(v);
+    if (live && h == 0) ys[t * m + r] = y;
+#pragma unroll
+    for (int k = 3; k > 0; --k)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) yh[k][j] = yh[k - 1][j];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) yh[0][j] = __shfl(y, (h + 4 * j) * 4, 64);
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) lc[k][j] = ln[k][j];
+  }
+  __syncthreads();
+  // backward: x_t = Dinv_t^T (y_t - sum_k L[t+k][k]^T x_{t+k}); lane holds
+  // column r of L[t+k][k] at rows h + 4j, and of Dinv_t
+  double xh[4][4] = {};                 // xh[k-1][j] = x_{t+k}[h + 4j]
+  auto load_bwd = [&](int t, double (&dst)[5][4]) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int q = h + 4 * j;
+        dst[k][j] = (live && q < m && t >= 0 && t + k < T) ? (double)Lb[bb_at(base, t + k, k, m) + (long long)q * m + r]
+                                                           : 0.0;
+      }
+  };
+  load_bwd(T - 1, lc);
+  for (int t = T - 1; t >= 0; --t) {
+    load_bwd(t - 1, ln);
+    double s = (live && h == 0) ? ys[t * m + r] : 0.0;
+#pragma unroll
+    for (int k = 1; k <= 4; ++k)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) s -= lc[k][j] * xh[k - 1][j];
+    s = rowsum(s);
+    double v = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = h + 4 * j;
+      const double sq = __shfl(s, (q < 16 ? q : 15) * 4, 64);
+      if (q >= r && q < m) v += lc[0][j] * sq;
+    }
+    const double x = rowsum(v);
+    if (live && h == 0) X[(long long)t * m + r] = (TV)x;
+#pragma unroll
+    for (int k = 3; k > 0; --k)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) xh[k][j] = xh[k - 1][j];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) xh[0][j] = __shfl(x, (h + 4 * j) * 4, 64);
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) lc[k][j] = ln[k][j];
+  }
+}
+
+template <typename TV>
+void launch_bb_solve16(hipStream_t st, int ninst, const int* inst_list, const LInst* li, const TV* Lb, const TV* b,
+                       TV* x) {
+  if (ninst <= 0) return;
+  hipLaunchKernelGGL((k_bb_solve16<TV>), dim3(ninst), dim3(64), 0, st, inst_list, li, Lb, b, x);
+}
+template void launch_bb_solve16<float>(hipStream_t, int, const int*, const LInst*, const float*, const float*,
+                                       float*);
+template void launch_bb_solve16<double>(hipStream_t, int, const int*, const LInst*, const double*, const double*,
+                                        double*);
+
 template <typename TV>
 void launch_bb_solve(hipStream_t st, int ninst, const int* inst_list, const LInst* li, const TV* Lb, const TV* b,
                      TV* x) {

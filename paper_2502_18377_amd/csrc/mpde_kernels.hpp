@@ -41,6 +41,9 @@ template <typename TV>
 void launch_bb_solve(hipStream_t st, int ninst, const int* inst_list, const LInst* li, const TV* Lb, const TV* b,
                      TV* x);
 template <typename TV>
+void launch_bb_solve16(hipStream_t st, int ninst, const int* inst_list, const LInst* li, const TV* Lb, const TV* b,
+                       TV* x);
+template <typename TV>
 void launch_bb_solve64(hipStream_t st, int ninst, const int* inst_list, const LInst* li, const TV* Lb, const TV* b,
                        TV* x);
 void launch_band_chol(hipStream_t st, int nmat, double* A, const long long* off, const int* n, const int* bw,

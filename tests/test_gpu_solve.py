@@ -171,3 +171,39 @@ def test_repeated_solves_bitwise_identical(maker):
         for a, b in zip(prob.split(z), zs):
             assert np.array_equal(a.double().cpu().numpy(), b)
         assert np.array_equal(inf2["iters"], info["iters"])
+
+
+@pytest.mark.parametrize("shape", [(8, 16, 16), (5, 8, 128)])
+def test_fused_operator_parity(shape):
+    # The one-pass three-axis operator kernel: tiles with halos along x and
+    # wrapped whole-axis tiles along y (8x16x16), a y axis longer than one
+    # tile and the shortest time axis (5x8x128).  Driven to a tight
+    # tolerance, the one-pass and two-pass kernels reach the same FP64
+    # iterate, which solves the oracle's assembled normal equations; at
+    # 5x8x128 it is also compared with the oracle's direct solve.
+    insts = [as_dtype(W.reaction_diffusion_2d(i, shape=shape), "f32") for i in range(2)]
+    _, zf, inf_f = gpu_solve(insts, "f32", tol=1e-11, fused=1, out_f64=1)
+    _, zt, inf_t = gpu_solve(insts, "f32", tol=1e-11, fused=0, out_f64=1)
+    assert all(s == 0 for s in inf_f["status"]) and all(s == 0 for s in inf_t["status"]), (inf_f, inf_t)
+    for inst, a, b in zip(insts, zf, zt):
+        assert normal_relres(inst, a) <= 2e-11
+        assert rel(a, b) <= 1e-6
+    if shape == (5, 8, 128):
+        _check(insts[0], zf[0])
+
+
+def test_fused_operator_mixed_batch():
+    # Instances of different three-axis shapes in one batch (tiles of every
+    # kind in one launch; instances reaching their coarsest level early).
+    shapes = [(9, 16, 16), (9, 8, 128), (12, 32, 16), (9, 32, 32)]
+    insts = [as_dtype(W.reaction_diffusion_2d(i, shape=s), "f32") for i, s in enumerate(shapes)]
+    _, zf, inf_f = gpu_solve(insts, "f32", tol=1e-11, fused=1, out_f64=1)
+    _, zt, inf_t = gpu_solve(insts, "f32", tol=1e-11, fused=0, out_f64=1)
+    assert all(s == 0 for s in inf_f["status"]) and all(s == 0 for s in inf_t["status"]), (inf_f, inf_t)
+    for inst, a, b in zip(insts, zf, zt):
+        assert normal_relres(inst, a) <= 2e-11
+        assert rel(a, b) <= 1e-6
+    # each instance alone gives the batched answer
+    for k in (1, 3):
+        _, z1, _ = gpu_solve([insts[k]], "f32", tol=1e-11, fused=1, out_f64=1)
+        assert rel(z1[0], zf[k]) <= 1e-6
