@@ -272,6 +272,7 @@ void make_ftab(FTab& f, const std::vector<LInst>& h, int B, const std::vector<in
     if (!sel[b] || h[b].N == 0) continue;
     const LInst& q = h[b];
     if (q.per[0] || !q.per[1] || !q.per[2] || q.n[0] < 5 || q.n[1] < 4 || q.n[2] < 4) return;
+    if (4LL * q.N * 7 >= (1LL << 31)) return;   // buffer offsets of the kernel are 31-bit
     ++nsel;
     mnx = std::max(mnx, q.n[1]);
     mny = std::max(mny, q.n[2]);
@@ -321,7 +322,8 @@ void make_ftab(FTab& f, const std::vector<LInst>& h, int B, const std::vector<in
       }
   }
   f.bstart[B] = slot;
-  if (sizeof(float) * (2 * (size_t)f.g.uplane + 16 * (size_t)f.g.qplane) > 65536) return;   // LDS per block
+  f.g.uplane = (f.g.uplane + 1 + 3) & ~3;   // spare slot for idle threads' staging writes; 16-byte rows
+  if (sizeof(float) * (kFRing * (size_t)f.g.uplane + 16 * (size_t)f.g.qplane) > 160000) return;   // LDS per block
   for (int g0 = 0; g0 < B; g0 += 8) {
     size_t mt = 0;
     for (int b = g0; b < std::min(B, g0 + 8); ++b) mt = std::max(mt, per[b].size());

@@ -70,14 +70,34 @@ constexpr int kFMaxU = 2;   // staged u values per thread and plane
 
 __device__ __forceinline__ int fwrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-// Difference sums of the time window of a point at window position WP; the
-// ring tu holds the planes p-4 .. p+4, so the window starts at 4 - WP.
+// Raw buffer access: the resource (base, size) and the uniform byte offset
+// live in scalar registers, the per-thread byte offset in one vector
+// register, so a load costs no vector address arithmetic.
+using brsrc = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ brsrc mkbuf(const void* p, long long bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float bld(brsrc r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void bst(brsrc r, unsigned voff, unsigned soff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
+}
+// A per-thread offset past the end of every buffer the kernel uses (their
+// sizes are below 2^31 bytes, checked by the host, and offset + plane offset
+// stays below 2^32): the buffer range check returns 0 for such a load and
+// drops such a store.  Lanes whose result must not be written use it, so
+// that every memory instruction of the plane loop is issued unconditionally
+// and the compiler's wait counts stay exact across loop iterations.
+constexpr unsigned kOOB = 0x80000000u;
+
+// Difference sums of the time window w[0..4] of a point at window position WP.
 template <typename TA, int WP>
-__device__ __forceinline__ void t_sums(const TA* tu, TA& s1, TA& s2) {
-  s1 = CW1<TA, WP, 0>() * tu[4 - WP] + CW1<TA, WP, 1>() * tu[5 - WP] + CW1<TA, WP, 2>() * tu[6 - WP] +
-       CW1<TA, WP, 3>() * tu[7 - WP] + CW1<TA, WP, 4>() * tu[8 - WP];
-  s2 = CW2<TA, WP, 0>() * tu[4 - WP] + CW2<TA, WP, 1>() * tu[5 - WP] + CW2<TA, WP, 2>() * tu[6 - WP] +
-       CW2<TA, WP, 3>() * tu[7 - WP] + CW2<TA, WP, 4>() * tu[8 - WP];
+__device__ __forceinline__ void t_sums(const TA* w, TA& s1, TA& s2) {
+  s1 = CW1<TA, WP, 0>() * w[0] + CW1<TA, WP, 1>() * w[1] + CW1<TA, WP, 2>() * w[2] + CW1<TA, WP, 3>() * w[3] +
+       CW1<TA, WP, 4>() * w[4];
+  s2 = CW2<TA, WP, 0>() * w[0] + CW2<TA, WP, 1>() * w[1] + CW2<TA, WP, 2>() * w[2] + CW2<TA, WP, 3>() * w[3] +
+       CW2<TA, WP, 4>() * w[4];
 }
 // Scatter of a time row's projected difference residuals (already weighted
 // by wC1, wC2) into the partial results of the planes of its window.
@@ -106,17 +126,18 @@ __device__ __forceinline__ void xy_rows(const TA* su, int w0, int sd, TA ui, TA 
 }
 
 // Gather of the projected rows of a periodic axis staged in LDS into the
-// result at a tile point: q1/q2/qp/qm are the four row-value planes (already
-// weighted), `a` the point's slot, `sd` the slot stride along the axis.  Row
-// j + o contains j at window slot 2 - o; T+ of j - 1 and T- of j + 1 end at j.
-template <typename TA>
-__device__ __forceinline__ TA xy_gather(const TA* q1, const TA* q2, const TA* qp, const TA* qm, int a, int sd) {
-  TA y = qp[a] + qm[a] - qp[a - sd] - qm[a + sd];
-  y -= CW1<TA, 2, 4>() * q1[a - 2 * sd] + CW2<TA, 2, 4>() * q2[a - 2 * sd];
-  y -= CW1<TA, 2, 3>() * q1[a - sd] + CW2<TA, 2, 3>() * q2[a - sd];
-  y -= CW2<TA, 2, 2>() * q2[a];
-  y -= CW1<TA, 2, 1>() * q1[a + sd] + CW2<TA, 2, 1>() * q2[a + sd];
-  y -= CW1<TA, 2, 0>() * q1[a + 2 * sd] + CW2<TA, 2, 0>() * q2[a + 2 * sd];
+// result at a tile point.  Each slot holds the four weighted row residuals
+// of one point, (C1, C2, T+, T-); `a` is the point's slot, `sd` the slot
+// stride along the axis.  Row j + o contains j at window slot 2 - o; T+ of
+// j - 1 and T- of j + 1 end at j.
+__device__ __forceinline__ float xy_gather(const float4* q, int a, int sd) {
+  const float4 m2 = q[a - 2 * sd], m1 = q[a - sd], z = q[a], p1 = q[a + sd], p2 = q[a + 2 * sd];
+  float y = z.z + z.w - m1.z - p1.w;
+  y -= CW1<float, 2, 4>() * m2.x + CW2<float, 2, 4>() * m2.y;
+  y -= CW1<float, 2, 3>() * m1.x + CW2<float, 2, 3>() * m1.y;
+  y -= CW2<float, 2, 2>() * z.y;
+  y -= CW1<float, 2, 1>() * p1.x + CW2<float, 2, 1>() * p1.y;
+  y -= CW1<float, 2, 0>() * p2.x + CW2<float, 2, 0>() * p2.y;
   return y;
 }
 
@@ -144,98 +165,132 @@ __global__ void __launch_bounds__(kFThreads) k_apply3(const FTile* __restrict__ 
                                                       TV* __restrict__ xv, TV* __restrict__ rv,
                                                       TV* __restrict__ dv, const TV* __restrict__ dinv,
                                                       int cheb_step, double* __restrict__ partial) {
+  static_assert(std::is_same<TV, float>::value && std::is_same<TC, float>::value, "FP32 data");
+  constexpr int NQ = kFMaxQ;
   extern __shared__ __align__(16) unsigned char fsm[];
-  TA* su = reinterpret_cast<TA*>(fsm);     // [2][uplane] staged u planes
-  TA* sq = su + 2 * g.uplane;              // [2][8][qplane] projected x rows (0-3), y rows (4-7)
+  TA* su = reinterpret_cast<TA*>(fsm);     // [kFRing][uplane] staged u planes, plane p in slot p % kFRing
+  float4* sq = reinterpret_cast<float4*>(su + kFRing * g.uplane);   // [2][2][qplane] projected x, y rows
   const FTile tl = tiles[blockIdx.x];
   const LInst& L = li[tl.inst];
   const int nt = L.n[0], nx = L.n[1], ny = L.n[2];
   const FSpan X = fspan(tl.x0, g.TX, nx, 1);
   const FSpan Y = fspan(tl.y0, g.TY, ny, 1);
   const int stt = L.str[0], stx = L.str[1], sty = L.str[2];   // an instance level has < 2^31 points
-  const TV* U = u + L.voff;
-  const TC* Cf = c + L.coff;
   const int tid = threadIdx.x;
+  const int npts = X.qn * Y.qn;
 
-  // ---- the row point owned by this thread (the same (x, y) on every plane)
-  const bool act = tid < X.qn * Y.qn;
-  const int lx = act ? tid / Y.qn : 0, ly = act ? tid - lx * Y.qn : 0;
-  const int gx = fwrap(X.qlo + lx, nx), gy = fwrap(Y.qlo + ly, ny);
-  const int gof = gx * stx + gy * sty;
-  // staged u: the point sits at (lx + 2, ly + 2); its windows start 2 before
-  const int axw = lx * Y.un + (ly + 2);
-  const int ayw = (lx + 2) * Y.un + ly;
-  const int sx = lx + X.qoff, sy = ly + Y.qoff;
-  const int qsl = sx * Y.qs + sy;
-  int qdx = -1, qdy = -1;   // wrapped copies of a whole-axis tile
-  if (X.fw) {
-    if (lx < 2) qdx = (sx + nx) * Y.qs + sy;
-    else if (lx >= nx - 2) qdx = (sx - nx) * Y.qs + sy;
-  }
-  if (Y.fw) {
-    if (ly < 2) qdy = qsl + ny;
-    else if (ly >= ny - 2) qdy = qsl - ny;
-  }
-  const bool tile = act && (unsigned)(lx - X.ilo) < (unsigned)X.icnt && (unsigned)(ly - Y.ilo) < (unsigned)Y.icnt;
-
-  // ---- rings: tu[k] = u at plane p - 4 + k of the owned point; acc likewise
-  TA tu[9], acc[9];
+  // ---- the row points owned by this thread (the same (x, y) on every plane):
+  // q-point tid + s * kFThreads, s < NQ
+  bool act[NQ], tile[NQ];
+  int ad[NQ], axw[NQ], ayw[NQ], qsl[NQ], qdx[NQ], qdy[NQ];
+  unsigned go[NQ];   // byte offset of the point within a plane (0 if none)
+  unsigned gt[NQ];   // the same for tile points, kOOB for halo points
 #pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    const int pl = k - 4;
-    tu[k] = (act && pl >= 0 && pl < nt) ? (TA)U[pl * stt + gof] : (TA)0;
-    acc[k] = 0;
+  for (int s = 0; s < NQ; ++s) {
+    const int qi = tid + s * kFThreads;
+    act[s] = qi < npts;
+    const int lx = act[s] ? qi / Y.qn : 0, ly = act[s] ? qi - lx * Y.qn : 0;
+    const int gx = fwrap(X.qlo + lx, nx), gy = fwrap(Y.qlo + ly, ny);
+    go[s] = act[s] ? 4u * (unsigned)(gx * stx + gy * sty) : 0u;
+    // staged u: the point sits at (lx + 2, ly + 2); its windows start 2 before
+    ad[s] = (lx + 2) * Y.un + (ly + 2);
+    axw[s] = lx * Y.un + (ly + 2);
+    ayw[s] = (lx + 2) * Y.un + ly;
+    const int sx = lx + X.qoff, sy = ly + Y.qoff;
+    qsl[s] = sx * Y.qs + sy;
+    qdx[s] = qdy[s] = -1;   // wrapped copies of a whole-axis tile
+    if (X.fw) {
+      if (lx < 2) qdx[s] = (sx + nx) * Y.qs + sy;
+      else if (lx >= nx - 2) qdx[s] = (sx - nx) * Y.qs + sy;
+    }
+    if (Y.fw) {
+      if (ly < 2) qdy[s] = qsl[s] + ny;
+      else if (ly >= ny - 2) qdy[s] = qsl[s] - ny;
+    }
+    tile[s] = act[s] && (unsigned)(lx - X.ilo) < (unsigned)X.icnt && (unsigned)(ly - Y.ilo) < (unsigned)Y.icnt;
+    gt[s] = tile[s] ? go[s] : kOOB;
   }
-  // staged-u slot -> offset within a plane (fixed over the planes)
+
+  // Loads are raw buffer loads: a per-thread byte offset fixed over the
+  // planes and a uniform plane offset.  Slots without a row point load point
+  // 0 and planes past the end load the last plane; both are ignored.
+  const unsigned pbytes = 4u * (unsigned)stt;                 // one plane
+  const brsrc rU = mkbuf(u + L.voff, 4LL * L.N);
+  const brsrc rC = mkbuf(c + L.coff, 4LL * L.N * ci.K);
+  auto psoff = [&](int pl) { return (unsigned)(pl < nt ? pl : nt - 1) * pbytes; };
+  // coefficient plane offsets (bytes) of c_phi and of the first / second
+  // derivative of each axis; a missing field loads plane 0 and is zeroed by
+  // its scale factor below
+  unsigned cko[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) cko[k] = ci.k[k] >= 0 ? 4u * (unsigned)ci.k[k] * (unsigned)L.N : 0u;
+
+  // ---- partial results over the time axis: a register ring of length 10,
+  // shifted by two planes after every odd plane; on an even plane p,
+  // acc[s][k] holds plane p - 4 + k of point s, on an odd plane the same
+  // entries sit one slot higher.  The time windows of u are read from the
+  // staged planes (the ring keeps planes p - 4 .. p + 5).
+  TA acc[NQ][10];
+#pragma unroll
+  for (int s = 0; s < NQ; ++s)
+#pragma unroll
+    for (int k = 0; k < 10; ++k) acc[s][k] = 0;
+  auto slot = [&](int pl) { return (pl % kFRing) * g.uplane; };
+  // staged-u slot -> byte offset within a plane (fixed over the planes)
   const int nus = X.un * Y.un;
-  int uof[kFMaxU];
+  // (slots past the region load point 0 and are written to the spare slot
+  // at the end of the staged plane, which nothing reads)
+  unsigned uof[kFMaxU];
+  int uslot[kFMaxU];
 #pragma unroll
   for (int k = 0; k < kFMaxU; ++k) {
     const int i = tid + k * kFThreads;
-    uof[k] = -1;
+    uof[k] = 0;
+    uslot[k] = g.uplane - 1;
     if (i < nus) {
       const int ux = i / Y.un, uy = i - ux * Y.un;
-      uof[k] = fwrap(X.ulo + ux, nx) * stx + fwrap(Y.ulo + uy, ny) * sty;
+      uof[k] = 4u * (unsigned)(fwrap(X.ulo + ux, nx) * stx + fwrap(Y.ulo + uy, ny) * sty);
+      uslot[k] = i;
     }
   }
-  // coefficient planes of c_phi and of the first / second derivative of
-  // each axis (null: no such field)
-  const TC* cpl[7];
-#pragma unroll
-  for (int k = 0; k < 7; ++k) cpl[k] = ci.k[k] >= 0 ? Cf + (long long)ci.k[k] * L.N : nullptr;
 
   // Loads run two planes ahead of their use, into register sets indexed by
   // plane parity; the plane loop is unrolled by two so that every set has a
   // fixed register name (a register copy would wait for the load):
   //   cs[q]  coefficients of the next plane of parity q to be processed,
-  //   us[q]  u of the next plane of parity q to be staged in LDS,
-  //   ts[q]  the next time-ring entry of parity q.
-  TA cs[2][7], us[2][kFMaxU], ts[2];
-  auto ld_coef = [&](int pl, TA(&d)[7]) {
+  //   us[q]  u of the next plane of parity q to be staged in LDS.
+  TA cs[2][NQ][7], us[2][kFMaxU];
+  auto ld_coef = [&](int pl, TA(&d)[NQ][7]) {
+    const unsigned po = psoff(pl);
 #pragma unroll
-    for (int k = 0; k < 7; ++k) d[k] = (act && cpl[k] && pl < nt) ? (TA)cpl[k][pl * stt + gof] : (TA)0;
+    for (int s = 0; s < NQ; ++s)
+#pragma unroll
+      for (int k = 0; k < 7; ++k) d[s][k] = bld(rC, go[s], cko[k] + po);
   };
   auto ld_u = [&](int pl, TA(&d)[kFMaxU]) {
+    const unsigned po = psoff(pl);
 #pragma unroll
-    for (int k = 0; k < kFMaxU; ++k) d[k] = (uof[k] >= 0 && pl < nt) ? (TA)U[pl * stt + uof[k]] : (TA)0;
+    for (int k = 0; k < kFMaxU; ++k) d[k] = bld(rU, uof[k], po);
   };
-  auto ld_t = [&](int pl) -> TA { return (act && pl < nt) ? (TA)U[pl * stt + gof] : (TA)0; };
+  // planes 0..4 staged before the loop; plane p + 5 is staged at plane p
+  for (int pl = 0; pl < 5; ++pl) {
+    const unsigned po = psoff(pl);
 #pragma unroll
-  for (int k = 0; k < kFMaxU; ++k)
-    if (uof[k] >= 0) su[tid + k * kFThreads] = (TA)U[uof[k]];
+    for (int k = 0; k < kFMaxU; ++k) su[slot(pl) + uslot[k]] = bld(rU, uof[k], po);
+  }
   ld_coef(0, cs[0]);
   ld_coef(1, cs[1]);
-  ld_u(1, us[1]);
-  ld_u(2, us[0]);
-  ts[1] = ld_t(5);
-  ts[0] = ld_t(6);
+  ld_u(5, us[0]);
+  ld_u(6, us[1]);
   __syncthreads();
 
   const TA wT0 = (TA)L.wT[0], wC10 = (TA)L.wC1[0], wC20 = (TA)L.wC2[0];
   const TA wTx = (TA)L.wT[1], wC1x = (TA)L.wC1[1], wC2x = (TA)L.wC2[1];
   const TA wTy = (TA)L.wT[2], wC1y = (TA)L.wC1[2], wC2y = (TA)L.wC2[2];
-  const TA s1t = (TA)L.is1[0], s2t = (TA)L.is2[0], s1x = (TA)L.is1[1], s2x = (TA)L.is2[1];
-  const TA s1y = (TA)L.is1[2], s2y = (TA)L.is2[2];
+  auto has = [&](int k) { return ci.k[k] >= 0 ? (TA)1 : (TA)0; };
+  const TA m0 = has(0);
+  const TA s1t = (TA)L.is1[0] * has(1), s2t = (TA)L.is2[0] * has(2), s1x = (TA)L.is1[1] * has(3);
+  const TA s2x = (TA)L.is2[1] * has(4), s1y = (TA)L.is1[2] * has(5), s2y = (TA)L.is2[2] * has(6);
   const TA gx11 = (TA)L.gi[1][0][0], gx12 = (TA)L.gi[1][0][1], gx22 = (TA)L.gi[1][0][2];
   const TA gy11 = (TA)L.gi[2][0][0], gy12 = (TA)L.gi[2][0][1], gy22 = (TA)L.gi[2][0][2];
 
@@ -251,24 +306,46 @@ __global__ void __launch_bounds__(kFThreads) k_apply3(const FTile* __restrict__ 
   const TA ith = (TA)(1.0 / L.cheb_theta);
   double dot = 0;
 
-  auto finalize = [&](int j, TA y, TA uj) {
-    const long long gj = L.voff + j * stt + gof;
-    if (MODE == G_STORE) {
-      out[gj] = (TV)y;
-    } else if (MODE == G_STORE_DOT) {
-      out[gj] = (TV)y;
-      dot += (double)uj * (double)y;
-    } else if (MODE == G_RESID) {
-      const TA r = (bvec ? (TA)bvec[gj] : (TA)0) - y;
-      out[gj] = (TV)r;
-      if (dv) dv[gj] = (TV)((TA)dinv[gj] * r * ith);
-    } else {   // G_CHEB
-      xv[gj] = (TV)((TA)xv[gj] + uj);
-      const TA r = (TA)rv[gj] - y;
-      rv[gj] = (TV)r;
-      dv[gj] = (TV)(chA * uj + chB * (TA)dinv[gj] * r);
+  // Epilogue inputs of plane j (x, r, dinv for a Chebyshev step; b, dinv for
+  // a residual), loaded one plane before the epilogue runs.
+  const long long vb = 4LL * L.N;
+  const brsrc rOut = mkbuf(out ? out + L.voff : nullptr, out ? vb : 0);
+  const brsrc rB = mkbuf(bvec ? bvec + L.voff : nullptr, bvec ? vb : 0);
+  const brsrc rX = mkbuf(xv ? xv + L.voff : nullptr, xv ? vb : 0);
+  const brsrc rR = mkbuf(rv ? rv + L.voff : nullptr, rv ? vb : 0);
+  const brsrc rD = mkbuf(dv ? dv + L.voff : nullptr, dv ? vb : 0);
+  const brsrc rDi = mkbuf(dinv + L.voff, vb);
+  auto ld_epi = [&](int j, unsigned o, TA(&e)[3]) {
+    const unsigned pj = (unsigned)j * pbytes;
+    e[0] = e[1] = e[2] = 0;
+    if (MODE == G_RESID) {
+      if (bvec) e[0] = bld(rB, o, pj);
+      if (dv) e[2] = bld(rDi, o, pj);
+    } else if (MODE == G_CHEB) {
+      e[0] = bld(rX, o, pj);
+      e[1] = bld(rR, o, pj);
+      e[2] = bld(rDi, o, pj);
     }
   };
+  auto finalize = [&](int j, unsigned o, TA y, TA uj, const TA(&e)[3]) {
+    const unsigned pj = (unsigned)j * pbytes;
+    if (MODE == G_STORE) {
+      bst(rOut, o, pj, y);
+    } else if (MODE == G_STORE_DOT) {
+      bst(rOut, o, pj, y);
+      if (o != kOOB) dot += (double)uj * (double)y;
+    } else if (MODE == G_RESID) {
+      const TA r = e[0] - y;
+      bst(rOut, o, pj, r);
+      if (dv) bst(rD, o, pj, e[2] * r * ith);
+    } else {   // G_CHEB
+      bst(rX, o, pj, e[0] + uj);
+      const TA r = e[1] - y;
+      bst(rR, o, pj, r);
+      bst(rD, o, pj, chA * uj + chB * e[2] * r);
+    }
+  };
+  TA es[2][NQ][3];                   // epilogue inputs by plane parity
 
   // One plane.  Phase A evaluates the rows at plane p (staged u slot p & 1)
   // and stores the projected x and y rows in row buffer p & 1, then stages
@@ -279,39 +356,39 @@ __global__ void __launch_bounds__(kFThreads) k_apply3(const FTile* __restrict__ 
   // first two planes, 3, 4 on the last two, 2 elsewhere), a template
   // constant so that every ring index is fixed at compile time.
   auto step = [&](int p, auto par, auto wpc) {
-    constexpr int Q = decltype(par)::value;   // p & 1
+    constexpr int Q = decltype(par)::value;   // p & 1, also the ring offset
     constexpr int WP = decltype(wpc)::value;
     constexpr int tpt = WP != 4, tmt = WP != 0;
     constexpr int clt = tmt ? (tpt ? 0 : 2) : 1;
-    const TA* cu = su + Q * g.uplane;
-    TA* nu = su + (1 - Q) * g.uplane;
-    TA* qb = sq + Q * 8 * g.qplane;
-    TA* q1x = qb;
-    TA* q2x = qb + g.qplane;
-    TA* qpx = qb + 2 * g.qplane;
-    TA* qmx = qb + 3 * g.qplane;
-    TA* q1y = qb + 4 * g.qplane;
-    TA* q2y = qb + 5 * g.qplane;
-    TA* qpy = qb + 6 * g.qplane;
-    TA* qmy = qb + 7 * g.qplane;
+    const TA* cu = su + slot(p);
+    TA* nu = su + slot(p + 5);
+    const int tw0 = slot(p - WP), tw1 = slot(p - WP + 1), tw2 = slot(p - WP + 2), tw3 = slot(p - WP + 3),
+              tw4 = slot(p - WP + 4);
+    float4* qx = sq + Q * 2 * g.qplane;
+    float4* qy = qx + g.qplane;
     const TA gt11 = (TA)L.gi[0][clt][0], gt12 = (TA)L.gi[0][clt][1], gt22 = (TA)L.gi[0][clt][2];
     const bool onB = (L.dlo[0] && p == 0) || (L.dhi[0] && p == nt - 1);
 
-    if (act) {
-      const TA* cc = cs[Q];
-      const TA ui = tu[4];
+#pragma unroll
+    for (int s = 0; s < NQ; ++s) {
+      if (!act[s]) continue;
+      TA* const ra = acc[s] + Q;
+      const TA* cc = cs[Q][s];
+      // time window of the point (planes p - WP .. p - WP + 4)
+      const TA w[5] = {su[tw0 + ad[s]], su[tw1 + ad[s]], su[tw2 + ad[s]], su[tw3 + ad[s]], su[tw4 + ad[s]]};
+      const TA ui = w[WP];
       // time rows
       TA a1, a2;
-      t_sums<TA, WP>(tu, a1, a2);
-      const TA rTpt = tpt ? wT0 * (ui - tu[5]) : (TA)0;
-      const TA rTmt = tmt ? wT0 * (ui - tu[3]) : (TA)0;
+      t_sums<TA, WP>(w, a1, a2);
+      const TA rTpt = tpt ? wT0 * (ui - w[tpt ? WP + 1 : WP]) : (TA)0;
+      const TA rTmt = tmt ? wT0 * (ui - w[tmt ? WP - 1 : WP]) : (TA)0;
       const TA rC1t = -wC10 * a1, rC2t = -wC20 * a2;
       // x and y rows
       TA rTpx, rTmx, rC1x, rC2x, rTpy, rTmy, rC1y, rC2y;
-      xy_rows<TA>(cu, axw, Y.un, ui, wTx, wC1x, wC2x, rTpx, rTmx, rC1x, rC2x);
-      xy_rows<TA>(cu, ayw, 1, ui, wTy, wC1y, wC2y, rTpy, rTmy, rC1y, rC2y);
+      xy_rows<TA>(cu, axw[s], Y.un, ui, wTx, wC1x, wC2x, rTpx, rTmx, rC1x, rC2x);
+      xy_rows<TA>(cu, ayw[s], 1, ui, wTy, wC1y, wC2y, rTpy, rTmy, rC1y, rC2y);
       // Sherman-Morrison scalar gamma
-      const TA c0 = cc[0];
+      const TA c0 = cc[0] * m0;
       const TA cat = cc[1] * s1t, catt = cc[2] * s2t;
       const TA cax = cc[3] * s1x, caxx = cc[4] * s2x;
       const TA cay = cc[5] * s1y, cayy = cc[6] * s2y;
@@ -347,8 +424,10 @@ __global__ void __launch_bounds__(kFThreads) k_apply3(const FTile* __restrict__ 
         const TA Q1 = wC1x * (rC1x + wC1x * x1), Q2 = wC2x * (rC2x + wC2x * x2);
         const TA Tp = wTx * (rTpx + wTx * (x1 + (TA)0.5 * x2));
         const TA Tm = wTx * (rTmx + wTx * (-x1 + (TA)0.5 * x2));
-        q1x[qsl] = Q1; q2x[qsl] = Q2; qpx[qsl] = Tp; qmx[qsl] = Tm;
-        if (qdx >= 0) { q1x[qdx] = Q1; q2x[qdx] = Q2; qpx[qdx] = Tp; qmx[qdx] = Tm; }
+        const int a = qsl[s];
+        const float4 v = make_float4(Q1, Q2, Tp, Tm);
+        qx[a] = v;
+        if (qdx[s] >= 0) qx[qdx[s]] = v;
       }
       {
         const TA e1 = b1y + cay * gam, e2 = b2y + cayy * gam;
@@ -356,10 +435,12 @@ __global__ void __launch_bounds__(kFThreads) k_apply3(const FTile* __restrict__ 
         const TA Q1 = wC1y * (rC1y + wC1y * x1), Q2 = wC2y * (rC2y + wC2y * x2);
         const TA Tp = wTy * (rTpy + wTy * (x1 + (TA)0.5 * x2));
         const TA Tm = wTy * (rTmy + wTy * (-x1 + (TA)0.5 * x2));
-        q1y[qsl] = Q1; q2y[qsl] = Q2; qpy[qsl] = Tp; qmy[qsl] = Tm;
-        if (qdy >= 0) { q1y[qdy] = Q1; q2y[qdy] = Q2; qpy[qdy] = Tp; qmy[qdy] = Tm; }
+        const int a = qsl[s];
+        const float4 v = make_float4(Q1, Q2, Tp, Tm);
+        qy[a] = v;
+        if (qdy[s] >= 0) qy[qdy[s]] = v;
       }
-      if (tile) {
+      if (tile[s]) {
         const TA e1 = b1t + cat * gam, e2 = b2t + catt * gam;
         const TA x1 = -(gt11 * e1 + gt12 * e2), x2 = -(gt12 * e1 + gt22 * e2);
         const TA Q1 = wC10 * (rC1t + wC10 * x1), Q2 = wC20 * (rC2t + wC20 * x2);
@@ -367,37 +448,51 @@ __global__ void __launch_bounds__(kFThreads) k_apply3(const FTile* __restrict__ 
         const TA Tm = tmt ? wT0 * (rTmt + wT0 * (-x1 + (TA)0.5 * x2)) : (TA)0;
         TA e = c0 * gam + Tp + Tm;                     // equation row (q_E = gamma), own Taylor rows
         if (onB) e += ui;                              // boundary row
-        acc[4] += e;
-        acc[5] -= Tp;                                  // T+ of plane p ends at p + 1
-        acc[3] -= Tm;                                  // T- of plane p ends at p - 1
-        t_push<TA, WP>(acc, Q1, Q2);
+        ra[4] += e;
+        ra[5] -= Tp;                                   // T+ of plane p ends at p + 1
+        ra[3] -= Tm;                                   // T- of plane p ends at p - 1
+        t_push<TA, WP>(ra, Q1, Q2);
       }
     }
     ld_coef(p + 2, cs[Q]);
-    if (p + 1 < nt) {
+    // stage plane p + 5 (the slot of plane p - 5, which no reader needs any
+    // more; planes past the end stage a copy of the last plane, never read)
 #pragma unroll
-      for (int k = 0; k < kFMaxU; ++k)
-        if (uof[k] >= 0) nu[tid + k * kFThreads] = us[1 - Q][k];
+    for (int k = 0; k < kFMaxU; ++k) nu[uslot[k]] = us[Q][k];
+    ld_u(p + 7, us[Q]);
+    if (WP != 0) {
+#pragma unroll
+      for (int s = 0; s < NQ; ++s) ld_epi(p - 1 < nt ? p - 1 : nt - 1, gt[s], es[1 - Q][s]);
     }
-    ld_u(p + 3, us[1 - Q]);
     __syncthreads();
-    if (tile) {
-      acc[4] += xy_gather<TA>(q1x, q2x, qpx, qmx, qsl, Y.qs) + xy_gather<TA>(q1y, q2y, qpy, qmy, qsl, 1);
+#pragma unroll
+    for (int s = 0; s < NQ; ++s) {
+      TA* const ra = acc[s] + Q;
+      if (tile[s])
+        ra[4] += xy_gather(qx, qsl[s], Y.qs) + xy_gather(qy, qsl[s], 1);
       // plane p - 2 is complete unless it is one of the last five planes
-      if (p >= 2 && p - 2 < nt - 5) finalize(p - 2, acc[2], tu[2]);
+      // (those are written after the last plane)
+      if (WP >= 2) finalize(p - 2, (p - 2 < nt - 5) ? gt[s] : kOOB, ra[2], su[slot(p - 2) + ad[s]], es[Q][s]);
       if (WP == 4) {   // p = nt - 1
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
           const int j = p - 4 + k;
-          if (j >= 0 && j >= nt - 5) finalize(j, acc[k], tu[k]);
+          if (j >= 0 && j >= nt - 5) {
+            TA e[3];
+            ld_epi(j, gt[s], e);
+            finalize(j, gt[s], ra[k], su[slot(j) + ad[s]], e);
+          }
         }
       }
     }
+    if (Q == 1) {   // shift both rings by two planes
 #pragma unroll
-    for (int k = 0; k < 8; ++k) { tu[k] = tu[k + 1]; acc[k] = acc[k + 1]; }
-    tu[8] = ts[1 - Q];
-    acc[8] = 0;
-    ts[1 - Q] = ld_t(p + 7);
+      for (int s = 0; s < NQ; ++s) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[s][k] = acc[s][k + 2];
+        acc[s][8] = acc[s][9] = 0;
+      }
+    }
   };
   using I0 = std::integral_constant<int, 0>;
   using I1 = std::integral_constant<int, 1>;
@@ -430,8 +525,10 @@ void launch_apply3(hipStream_t st, const FTile* tiles, int nb, FGeom g, const LI
                    const TC* c, int mode, TV* out, const TV* bvec, TV* x, TV* r, TV* d, const TV* dinv,
                    int cheb_step, double* partial) {
   if (nb <= 0) return;
-  const size_t lds = sizeof(TA) * (2 * (size_t)g.uplane + 16 * (size_t)g.qplane);
+  const size_t lds = sizeof(TA) * (kFRing * (size_t)g.uplane + 16 * (size_t)g.qplane);   // qplane: float4 slots x 4
 #define MPDE_APPLY3(M)                                                                                          \
+  (void)hipFuncSetAttribute((const void*)k_apply3<TA, TV, TC, M>, hipFuncAttributeMaxDynamicSharedMemorySize,   \
+                            (int)lds);                                                                          \
   hipLaunchKernelGGL((k_apply3<TA, TV, TC, M>), dim3((unsigned)nb), dim3(kFThreads), lds, st, tiles, g, li, ci, u, \
                      c, out, bvec, x, r, d, dinv, cheb_step, partial)
   switch (mode) {

@@ -7,6 +7,7 @@ namespace mpde {
 
 constexpr int kFThreads = 768;   // threads per block
 constexpr int kFMaxQ = 1;        // row points per thread and plane
+constexpr int kFRing = 10;       // staged u planes kept in LDS
 
 // One block: an instance and the origin of its (x, y) tile; the block marches
 // over every time plane.
