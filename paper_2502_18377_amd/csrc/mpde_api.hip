@@ -307,6 +307,7 @@ void make_ftab(FTab& f, const std::vector<LInst>& h, int B, const std::vector<in
   f.g.TX = TX;
   f.g.TY = TY;
   f.g.uplane = f.g.qplane = 0;
+  f.g.nt = -1;
   std::vector<std::vector<FTile>> per(B);
   int slot = 0;
   for (int b = 0; b < B; ++b) {
@@ -319,6 +320,7 @@ void make_ftab(FTab& f, const std::vector<LInst>& h, int B, const std::vector<in
         f.g.uplane = std::max(f.g.uplane, X.un * Y.un);
         f.g.qplane = std::max(f.g.qplane, X.qs * Y.qs);
         per[b].push_back(FTile{b, x0, y0, slot++});
+        f.g.nt = (f.g.nt == -1 || f.g.nt == q.n[0]) ? q.n[0] : 0;
       }
   }
   f.bstart[B] = slot;

@@ -157,7 +157,7 @@ __device__ __forceinline__ double fblock_sum(double v) {
   return s;
 }
 
-template <typename TA, typename TV, typename TC, int MODE>
+template <typename TA, typename TV, typename TC, int MODE, int NT>
 __global__ void __launch_bounds__(kFThreads) k_apply3(const FTile* __restrict__ tiles, FGeom g,
                                                       const LInst* __restrict__ li, CIdx ci,
                                                       const TV* __restrict__ u, const TC* __restrict__ c,
@@ -172,7 +172,10 @@ __global__ void __launch_bounds__(kFThreads) k_apply3(const FTile* __restrict__ 
   float4* sq = reinterpret_cast<float4*>(su + kFRing * g.uplane);   // [2][2][qplane] projected x, y rows
   const FTile tl = tiles[blockIdx.x];
   const LInst& L = li[tl.inst];
-  const int nt = L.n[0], nx = L.n[1], ny = L.n[2];
+  // NT > 0: every instance of the launch has NT time planes (a compile-time
+  // trip count: the plane loop is unrolled completely and no prefetched
+  // value is carried around a loop)
+  const int nt = NT > 0 ? NT : L.n[0], nx = L.n[1], ny = L.n[2];
   const FSpan X = fspan(tl.x0, g.TX, nx, 1);
   const FSpan Y = fspan(tl.y0, g.TY, ny, 1);
   const int stt = L.str[0], stx = L.str[1], sty = L.str[2];   // an instance level has < 2^31 points
@@ -454,6 +457,11 @@ __global__ void __launch_bounds__(kFThreads) k_apply3(const FTile* __restrict__ 
         t_push<TA, WP>(ra, Q1, Q2);
       }
     }
+    // Keep the refills of the parity sets after the last use of their old
+    // contents: if the scheduler hoists them, the old and new values overlap,
+    // the sets cannot keep one register each across the loop, and the copies
+    // inserted at the loop latch wait for every load in flight.
+    __builtin_amdgcn_sched_barrier(0);
     ld_coef(p + 2, cs[Q]);
     // stage plane p + 5 (the slot of plane p - 5, which no reader needs any
     // more; planes past the end stage a copy of the last plane, never read)
@@ -502,6 +510,7 @@ __global__ void __launch_bounds__(kFThreads) k_apply3(const FTile* __restrict__ 
   step(0, I0(), I0());
   step(1, I1(), I1());
   int p = 2;
+#pragma unroll
   for (; p + 1 <= nt - 3; p += 2) {
     step(p, I0(), I2());
     step(p + 1, I1(), I2());
@@ -520,24 +529,48 @@ __global__ void __launch_bounds__(kFThreads) k_apply3(const FTile* __restrict__ 
   }
 }
 
+template <typename TA, typename TV, typename TC, int M, int T>
+static void apply3_one(hipStream_t st, const FTile* tiles, int nb, FGeom g, const LInst* li, CIdx ci, const TV* u,
+                       const TC* c, TV* out, const TV* bvec, TV* x, TV* r, TV* d, const TV* dinv, int cheb_step,
+                       double* partial, size_t lds) {
+  (void)hipFuncSetAttribute((const void*)k_apply3<TA, TV, TC, M, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+  hipLaunchKernelGGL((k_apply3<TA, TV, TC, M, T>), dim3((unsigned)nb), dim3(kFThreads), lds, st, tiles, g, li, ci,
+                     u, c, out, bvec, x, r, d, dinv, cheb_step, partial);
+}
+
+template <typename TA, typename TV, typename TC, int M>
+static void apply3_mode(hipStream_t st, const FTile* tiles, int nb, FGeom g, const LInst* li, CIdx ci, const TV* u,
+                        const TC* c, TV* out, const TV* bvec, TV* x, TV* r, TV* d, const TV* dinv, int cheb_step,
+                        double* partial, size_t lds) {
+  // (the dot-product variant keeps the loop: unrolled, it spills)
+  if (g.nt == 32 && M != G_STORE_DOT)
+    apply3_one<TA, TV, TC, M, M != G_STORE_DOT ? 32 : 0>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial, lds);
+  else
+    apply3_one<TA, TV, TC, M, 0>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial, lds);
+}
+
 template <typename TA, typename TV, typename TC>
 void launch_apply3(hipStream_t st, const FTile* tiles, int nb, FGeom g, const LInst* li, CIdx ci, const TV* u,
                    const TC* c, int mode, TV* out, const TV* bvec, TV* x, TV* r, TV* d, const TV* dinv,
                    int cheb_step, double* partial) {
   if (nb <= 0) return;
   const size_t lds = sizeof(TA) * (kFRing * (size_t)g.uplane + 16 * (size_t)g.qplane);   // qplane: float4 slots x 4
-#define MPDE_APPLY3(M)                                                                                          \
-  (void)hipFuncSetAttribute((const void*)k_apply3<TA, TV, TC, M>, hipFuncAttributeMaxDynamicSharedMemorySize,   \
-                            (int)lds);                                                                          \
-  hipLaunchKernelGGL((k_apply3<TA, TV, TC, M>), dim3((unsigned)nb), dim3(kFThreads), lds, st, tiles, g, li, ci, u, \
-                     c, out, bvec, x, r, d, dinv, cheb_step, partial)
   switch (mode) {
-    case G_STORE: MPDE_APPLY3(G_STORE); break;
-    case G_RESID: MPDE_APPLY3(G_RESID); break;
-    case G_CHEB: MPDE_APPLY3(G_CHEB); break;
-    default: MPDE_APPLY3(G_STORE_DOT); break;
+    case G_STORE:
+      apply3_mode<TA, TV, TC, G_STORE>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial, lds);
+      break;
+    case G_RESID:
+      apply3_mode<TA, TV, TC, G_RESID>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial, lds);
+      break;
+    case G_CHEB:
+      apply3_mode<TA, TV, TC, G_CHEB>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial, lds);
+      break;
+    default:
+      apply3_mode<TA, TV, TC, G_STORE_DOT>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial,
+                                           lds);
+      break;
   }
-#undef MPDE_APPLY3
 }
 
 template void launch_apply3<float, float, float>(hipStream_t, const FTile*, int, FGeom, const LInst*, CIdx,

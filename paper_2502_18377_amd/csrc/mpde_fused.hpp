@@ -19,7 +19,8 @@ struct FTile {
 struct FGeom {
   int TX, TY;        // tile extent in x and y
   int uplane;        // elements of one staged u plane
-  int qplane;        // elements of one staged row-value plane
+  int qplane;        // float4 slots of one staged row-value plane
+  int nt;            // time planes of every instance of the launch, 0 if they differ
 };
 
 // Ranges of one axis for a tile [x0, x0 + T) of an axis with n points:
