@@ -446,6 +446,59 @@ __global__ void __launch_bounds__(kBlock) k_cheb_init(const Work* __restrict__ w
 
 // Restriction r_c = P^T r_f / 2^(coarsened axes) over coarse points; P is
 // linear interpolation along the halved (spatial) axes.
+// One-dimensional transfer stencils along one axis.  Restriction (full
+// weighting, the transpose of linear interpolation): coarse X gathers fine
+// 2X (weight 1) and 2X-1, 2X+1 (weight 1/2; periodic wrap; on a non-periodic
+// axis the last fine point, extrapolated as a constant, gives its whole
+// weight).  Prolongation: fine i = 2X copies coarse X, i = 2X+1 averages X
+// and X+1 (wrap; constant extrapolation past the last coarse point).  An
+// axis that is not coarsened is the identity.  Entries with weight 0 carry a
+// valid index, so every load stays in bounds.
+struct Tap3 {
+  int i[3];
+  float w[3];
+};
+__device__ __forceinline__ Tap3 restrict_taps(int X, int nf, int ncn, int per, bool halved) {
+  Tap3 t;
+  if (!halved) {
+    t.i[0] = t.i[1] = t.i[2] = X;
+    t.w[0] = 1.f; t.w[1] = t.w[2] = 0.f;
+    return t;
+  }
+  t.i[0] = 2 * X;
+  t.w[0] = 1.f;
+  if (per) {
+    t.i[1] = 2 * X - 1 < 0 ? nf - 1 : 2 * X - 1;
+    t.i[2] = 2 * X + 1 >= nf ? 0 : 2 * X + 1;
+    t.w[1] = t.w[2] = 0.5f;
+  } else {
+    t.i[1] = X >= 1 ? 2 * X - 1 : 2 * X;
+    t.w[1] = X >= 1 ? 0.5f : 0.f;
+    const bool in = 2 * X + 1 < nf;
+    t.i[2] = in ? 2 * X + 1 : 2 * X;
+    t.w[2] = in ? ((X + 1 < ncn) ? 0.5f : 1.f) : 0.f;
+  }
+  return t;
+}
+struct Tap2 {
+  int i[2];
+  float w[2];
+};
+__device__ __forceinline__ Tap2 prolong_taps(int i, int ncn, int per, bool halved) {
+  Tap2 t;
+  if (!halved) { t.i[0] = t.i[1] = i; t.w[0] = 1.f; t.w[1] = 0.f; return t; }
+  const int X = i >> 1;
+  t.i[0] = X;
+  if ((i & 1) == 0) { t.i[1] = X; t.w[0] = 1.f; t.w[1] = 0.f; }
+  else if (per) { t.i[1] = X + 1 >= ncn ? 0 : X + 1; t.w[0] = t.w[1] = 0.5f; }
+  else if (X + 1 < ncn) { t.i[1] = X + 1; t.w[0] = t.w[1] = 0.5f; }
+  else { t.i[1] = X; t.w[0] = 1.f; t.w[1] = 0.f; }
+  return t;
+}
+
+// Restriction of fine residuals to coarse points: rc = P^T rf / 2^k, k =
+// number of halved axes.  Axis 0 (time) is never halved, so the stencil is
+// the tensor product of the two (or one) spatial axes.
 template <int D, typename TV>
 __global__ void __launch_bounds__(kBlock) k_restrict(const Work* __restrict__ work, const LInst* __restrict__ lf,
                                                      const LInst* __restrict__ lc, const TV* __restrict__ rf,
@@ -457,35 +510,24 @@ __global__ void __launch_bounds__(kBlock) k_restrict(const Work* __restrict__ wo
   if (jc >= C.N) return;
   int cc[kMaxD];
   coords<D>(C, jc, cc);
-  int fi[kMaxD][3];
-  double fw[kMaxD][3];
-  int cnt[kMaxD];
-  for (int a = 0; a < D; ++a) {
-    if (C.n[a] == F.n[a]) { cnt[a] = 1; fi[a][0] = cc[a]; fw[a][0] = 1; continue; }
-    const int nf = F.n[a], ncn = C.n[a], X = cc[a];
-    int m = 0;
-    fi[a][m] = 2 * X; fw[a][m++] = 1.0;
-    if (F.per[a]) {
-      fi[a][m] = (2 * X - 1 + nf) % nf; fw[a][m++] = 0.5;
-      fi[a][m] = (2 * X + 1) % nf; fw[a][m++] = 0.5;
-    } else {
-      if (X >= 1) { fi[a][m] = 2 * X - 1; fw[a][m++] = 0.5; }
-      if (2 * X + 1 < nf) { fi[a][m] = 2 * X + 1; fw[a][m++] = (X + 1 < ncn) ? 0.5 : 1.0; }
+  const TV* R = rf + F.voff + (long long)cc[0] * F.str[0];
+  const Tap3 a1 = restrict_taps(cc[1], F.n[1], C.n[1], F.per[1], C.n[1] != F.n[1]);
+  float acc = 0.f;
+  if (D == 2) {
+#pragma unroll
+    for (int u = 0; u < 3; ++u) acc += a1.w[u] * (float)R[a1.i[u]];
+  } else {
+    const Tap3 a2 = restrict_taps(cc[2], F.n[2], C.n[2], F.per[2], C.n[2] != F.n[2]);
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const TV* Ru = R + (long long)a1.i[u] * F.str[1];
+      float s = 0.f;
+#pragma unroll
+      for (int v = 0; v < 3; ++v) s += a2.w[v] * (float)Ru[a2.i[v]];
+      acc += a1.w[u] * s;
     }
-    cnt[a] = m;
   }
-  double acc = 0;
-  int idx[kMaxD] = {0, 0, 0};
-  const int tot = cnt[0] * cnt[1] * (D == 3 ? cnt[2] : 1);
-  for (int t = 0; t < tot; ++t) {
-    int rem = t;
-    long long off = 0;
-    double wgt = 1;
-    for (int a = D - 1; a >= 0; --a) { idx[a] = rem % cnt[a]; rem /= cnt[a]; }
-    for (int a = 0; a < D; ++a) { off += (long long)fi[a][idx[a]] * F.str[a]; wgt *= fw[a][idx[a]]; }
-    acc += wgt * (double)rf[F.voff + off];
-  }
-  rc[C.voff + jc] = (TV)(acc / (double)(1 << C.ncoarsened));
+  rc[C.voff + jc] = (TV)(acc * (1.f / (float)(1 << C.ncoarsened)));
 }
 
 // Prolongation and correction x_f += P e_c over fine points.
@@ -500,29 +542,21 @@ __global__ void __launch_bounds__(kBlock) k_prolong_add(const Work* __restrict__
   if (jf >= F.N) return;
   int fc[kMaxD];
   coords<D>(F, jf, fc);
-  int ci2[kMaxD][2];
-  double cw[kMaxD][2];
-  int cnt[kMaxD];
-  for (int a = 0; a < D; ++a) {
-    if (C.n[a] == F.n[a]) { cnt[a] = 1; ci2[a][0] = fc[a]; cw[a][0] = 1; continue; }
-    const int i = fc[a], X = i >> 1, ncn = C.n[a];
-    if ((i & 1) == 0) { cnt[a] = 1; ci2[a][0] = X; cw[a][0] = 1; }
-    else if (F.per[a]) { cnt[a] = 2; ci2[a][0] = X; cw[a][0] = 0.5; ci2[a][1] = (X + 1) % ncn; cw[a][1] = 0.5; }
-    else if (X + 1 < ncn) { cnt[a] = 2; ci2[a][0] = X; cw[a][0] = 0.5; ci2[a][1] = X + 1; cw[a][1] = 0.5; }
-    else { cnt[a] = 1; ci2[a][0] = X; cw[a][0] = 1; }
-  }
-  double acc = 0;
-  const int tot = cnt[0] * cnt[1] * (D == 3 ? cnt[2] : 1);
-  for (int t = 0; t < tot; ++t) {
-    int rem = t, idx[kMaxD];
-    for (int a = D - 1; a >= 0; --a) { idx[a] = rem % cnt[a]; rem /= cnt[a]; }
-    long long off = 0;
-    double wgt = 1;
-    for (int a = 0; a < D; ++a) { off += (long long)ci2[a][idx[a]] * C.str[a]; wgt *= cw[a][idx[a]]; }
-    acc += wgt * (double)ec[C.voff + off];
+  const TV* E = ec + C.voff + (long long)fc[0] * C.str[0];
+  const Tap2 a1 = prolong_taps(fc[1], C.n[1], F.per[1], C.n[1] != F.n[1]);
+  float acc = 0.f;
+  if (D == 2) {
+    acc = a1.w[0] * (float)E[a1.i[0]] + a1.w[1] * (float)E[a1.i[1]];
+  } else {
+    const Tap2 a2 = prolong_taps(fc[2], C.n[2], F.per[2], C.n[2] != F.n[2]);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const TV* Eu = E + (long long)a1.i[u] * C.str[1];
+      acc += a1.w[u] * (a2.w[0] * (float)Eu[a2.i[0]] + a2.w[1] * (float)Eu[a2.i[1]]);
+    }
   }
   const long long g = F.voff + jf;
-  xf[g] = (TV)((double)xf[g] + acc);
+  xf[g] = (TV)((float)xf[g] + acc);
 }
 
 // Coefficient coarsening: normalised full weighting along halved axes.
