@@ -686,16 +686,55 @@ __global__ void __launch_bounds__(kBlock) k_extract_band(const Work* __restrict_
   Lb[bb_at(bout[wk.inst], tr, k, m) + (long long)sr * m + sc] = Y[L.voff + i];
 }
 
-// Block Cholesky, one block of threads per instance, FP64.
+// Block Cholesky, one block of threads per instance, FP64.  The block
+// products (the off-diagonal blocks L_ij = B_ij L_jj^-T and the trailing
+// updates B_ik -= L_ij L_kj^T) run as 64 x 64 x 64 products C = A B^T with
+// both operands staged transposed in LDS and a 4 x 4 register tile per
+// thread (256 threads cover the 64 x 64 result); blocks of a smaller plane
+// are zero-padded to 64.
+constexpr int kBBT = kBBMax + 4;   // staged operand stride (keeps 4-double groups 16-byte aligned)
+
+// Stage the m x m row-major block G (global, or LDS when `lds_src`) into T
+// transposed and zero-padded: T[q][r] = G[r][q].
+__device__ __forceinline__ void bb_stage_t(double* __restrict__ T, const double* G, int m, int gstride) {
+  for (int e = threadIdx.x; e < kBBMax * kBBMax; e += kBlock) {
+    const int r = e >> 6, q = e & 63;
+    T[q * kBBT + r] = (r < m && q < m) ? G[r * gstride + q] : 0.0;
+  }
+}
+
+// acc[a][b] = sum_q At[q][4tr + a] * Bt[q][4tc + b] for the thread's tile.
+__device__ __forceinline__ void bb_tile_abt(const double* __restrict__ At, const double* __restrict__ Bt,
+                                            double (&acc)[4][4]) {
+  const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+#pragma unroll 4
+  for (int q = 0; q < kBBMax; ++q) {
+    const double2 a01 = *reinterpret_cast<const double2*>(At + q * kBBT + 4 * tr);
+    const double2 a23 = *reinterpret_cast<const double2*>(At + q * kBBT + 4 * tr + 2);
+    const double2 b01 = *reinterpret_cast<const double2*>(Bt + q * kBBT + 4 * tc);
+    const double2 b23 = *reinterpret_cast<const double2*>(Bt + q * kBBT + 4 * tc + 2);
+    const double av[4] = {a01.x, a01.y, a23.x, a23.y}, bv[4] = {b01.x, b01.y, b23.x, b23.y};
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+  }
+}
+
 __global__ void __launch_bounds__(kBlock) k_bb_factor(double* __restrict__ Lb, const long long* __restrict__ boff,
                                                       const int* __restrict__ Tn, const int* __restrict__ mn,
                                                       int* __restrict__ fail) {
   const long long base = boff[blockIdx.x];
   const int T = Tn[blockIdx.x], m = mn[blockIdx.x];
   __shared__ double Dg[kBBMax][kBBMax + 1];
-  __shared__ double Di[kBBMax][kBBMax + 1];
-  __shared__ double Ab[kBBMax][kBBMax + 1];
+  __shared__ __align__(16) double S1[kBBMax * kBBT];   // staged A^T
+  __shared__ __align__(16) double S2[kBBMax * kBBT];   // staged B^T
   const int tid = threadIdx.x;
+  const int tr = tid >> 4, tc = tid & 15;
   for (int j = 0; j < T; ++j) {
     double* Bjj = Lb + bb_at(base, j, 0, m);
     for (int e = tid; e < m * m; e += blockDim.x) Dg[e / m][e % m] = Bjj[e];
@@ -717,49 +756,61 @@ __global__ void __launch_bounds__(kBlock) k_bb_factor(double* __restrict__ Lb, c
       }
       __syncthreads();
     }
-    // inverse of the lower-triangular factor: column c by forward substitution
+    // inverse of the lower-triangular factor, column c by forward
+    // substitution, written transposed into S2: S2[q][c] = Linv[c][q], the
+    // staged B^T of the products B_ij Linv^T below
+    for (int e = tid; e < kBBMax * kBBT; e += blockDim.x) S2[e] = 0.0;
+    __syncthreads();
     for (int cc = tid; cc < m; cc += blockDim.x) {
-      for (int r = 0; r < m; ++r) {
+      for (int r = cc; r < m; ++r) {
         double acc = (r == cc) ? 1.0 : 0.0;
-        if (r < cc) { Di[r][cc] = 0.0; continue; }
-        for (int q = cc; q < r; ++q) acc -= Dg[r][q] * Di[q][cc];
-        Di[r][cc] = acc / Dg[r][r];
+        for (int q = cc; q < r; ++q) acc -= Dg[r][q] * S2[cc * kBBT + q];
+        S2[cc * kBBT + r] = acc / Dg[r][r];
       }
     }
     __syncthreads();
-    for (int e = tid; e < m * m; e += blockDim.x) Bjj[e] = Di[e / m][e % m];
+    // S2 holds Linv transposed per column: S2[c][r] = Linv[r][c]; the block
+    // stores Linv row-major (k_bb_solve* read the inverse there)
+    for (int e = tid; e < m * m; e += blockDim.x) {
+      const int r = e / m, cc = e % m;
+      Bjj[e] = S2[cc * kBBT + r];
+    }
+    // B^T operand of L_ij = B_ij Linv^T is Linv^T[q][c] = Linv[c][q] = S2[q][c]: in place.
     __syncthreads();
-    // off-diagonal blocks of column j: L_ij = B_ij * L_jj^-T
     const int ie = min(T - 1, j + 4);
     for (int i = j + 1; i <= ie; ++i) {
       double* Bij = Lb + bb_at(base, i, i - j, m);
-      for (int e = tid; e < m * m; e += blockDim.x) Ab[e / m][e % m] = Bij[e];
+      bb_stage_t(S1, Bij, m, m);
       __syncthreads();
-      for (int e = tid; e < m * m; e += blockDim.x) {
-        const int r = e / m, cc = e % m;
-        double acc = 0;
-        for (int q = 0; q <= cc; ++q) acc += Ab[r][q] * Di[cc][q];
-        Bij[e] = acc;
-      }
+      double acc[4][4];
+      bb_tile_abt(S1, S2, acc);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int r = 4 * tr + a, cc = 4 * tc + b;
+          if (r < m && cc < m) Bij[r * m + cc] = acc[a][b];
+        }
       __syncthreads();
     }
-    // trailing update: B_ik -= L_ij L_kj^T for j < k <= i <= j + 4, with
-    // L_kj staged in LDS (Di is free once the off-diagonal blocks are done)
+    // trailing update: B_ik -= L_ij L_kj^T for j < k <= i <= j + 4
     for (int k = j + 1; k <= ie; ++k) {
       const double* Lkj = Lb + bb_at(base, k, k - j, m);
-      for (int e = tid; e < m * m; e += blockDim.x) Di[e / m][e % m] = Lkj[e];
-      __syncthreads();
+      bb_stage_t(S2, Lkj, m, m);
       for (int i = k; i <= ie; ++i) {
         const double* Lij = Lb + bb_at(base, i, i - j, m);
-        for (int e = tid; e < m * m; e += blockDim.x) Ab[e / m][e % m] = Lij[e];
+        bb_stage_t(S1, Lij, m, m);
         __syncthreads();
+        double acc[4][4];
+        bb_tile_abt(S1, S2, acc);
         double* Bik = Lb + bb_at(base, i, i - k, m);
-        for (int e = tid; e < m * m; e += blockDim.x) {
-          const int r = e / m, cc = e % m;
-          double acc = 0;
-          for (int q = 0; q < m; ++q) acc += Ab[r][q] * Di[cc][q];
-          Bik[e] -= acc;
-        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int r = 4 * tr + a, cc = 4 * tc + b;
+            if (r < m && cc < m) Bik[r * m + cc] -= acc[a][b];
+          }
         __syncthreads();
       }
     }
