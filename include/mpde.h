@@ -170,7 +170,8 @@ const char *mpde_last_error(void);
 
 /* Kernel statistics of the last mpde_solve run with options.profile set:
  * one record per kernel family on the finest grid ("gamma": the per-point
- * projection pass, "gather": the operator/smoother pass), with launches,
+ * projection pass, "gather": the operator/smoother pass of the two-pass
+ * kernels, "apply3": the one-pass three-axis operator), with launches,
  * summed device time in ms (HIP events on the problem's stream) and the
  * algorithmic HBM bytes those launches must move (inputs read once, outputs
  * written once).  Writes at most max records to out (host) and returns the
@@ -182,6 +183,19 @@ typedef struct {
   double bytes;
 } mpde_kstat;
 int mpde_kernel_stats(const mpde_problem *p, mpde_kstat *out, int32_t max);
+
+/* Timing of the finest-grid operator pass (the matrix-free normal-equation
+ * operator of Eq. 9 in reduced form, fused with the epilogue `mode`: 0 y = S u,
+ * 1 residual, 2 Chebyshev smoothing step, 3 y = S u with per-block u.y
+ * partial sums): `reps` launches back to back on the problem's stream on the
+ * library's own level-0 work vectors, between two HIP events.  Writes the
+ * mean duration per launch in microseconds and the algorithmic HBM bytes of
+ * one launch (inputs read once, outputs written once).  Overwrites only
+ * library scratch vectors: a later mpde_solve or mpde_solve_adjoint is
+ * unaffected.  Returns MPDE_ERR_INVALID_ARG for a NULL problem or output,
+ * mode outside 0..3 or reps < 1. */
+int mpde_time_operator(mpde_problem *p, int32_t mode, int32_t reps, double *us_per_launch,
+                       double *bytes_per_launch);
 
 /* ---------------------------------------------------------------------
  * Learned coarse-grid correction (an addition to the paper's solver): a

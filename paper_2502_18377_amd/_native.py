@@ -15,7 +15,7 @@ BC_CODES = {"none": MPDE_BC_NONE, "dirichlet": MPDE_BC_DIRICHLET, "periodic": MP
 EXPORTS = ("mpde_default_options", "mpde_build", "mpde_solve", "mpde_solve_adjoint",
            "mpde_free", "mpde_last_error", "mpde_levels", "mpde_kernel_stats",
            "mpde_net_create", "mpde_net_train_step", "mpde_net_attach", "mpde_net_get", "mpde_net_set",
-           "mpde_net_free", "mpde_conv3d", "mpde_conv3d_wgrad", "mpde_autotune")
+           "mpde_net_free", "mpde_conv3d", "mpde_conv3d_wgrad", "mpde_autotune", "mpde_time_operator")
 NET_PARAMS = 3 * (27 * 16 * 16 + 16)
 
 
@@ -82,6 +82,9 @@ def load():
     lib.mpde_levels.restype = ctypes.c_int
     lib.mpde_kernel_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(KStat), ctypes.c_int32]
     lib.mpde_kernel_stats.restype = ctypes.c_int
+    lib.mpde_time_operator.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    lib.mpde_time_operator.restype = ctypes.c_int
     vp, i32, i64, u64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
     lib.mpde_net_create.argtypes = [i32, u64, ctypes.POINTER(vp)]
     lib.mpde_net_train_step.argtypes = [vp, vp, i32, u64, dbl, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]

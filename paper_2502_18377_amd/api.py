@@ -134,6 +134,14 @@ class Problem:
         return {arr[i].name.decode(): dict(launches=int(arr[i].launches), ms=arr[i].ms, bytes=arr[i].bytes)
                 for i in range(min(n, 4))}
 
+    def time_operator(self, mode=2, reps=20):
+        """Mean microseconds and algorithmic HBM bytes of one finest-grid
+        operator pass in `mode` (0 apply, 1 residual, 2 Chebyshev step, 3
+        apply with dot products), timed over `reps` back-to-back passes."""
+        us, by = ctypes.c_double(), ctypes.c_double()
+        N.check(self._lib.mpde_time_operator(self._h, mode, reps, ctypes.byref(us), ctypes.byref(by)))
+        return us.value, by.value
+
     def levels(self, b=0):
         n = self._lib.mpde_levels(self._h, b, None)
         arr = (ctypes.c_int32 * (n * self.D))()

@@ -211,7 +211,8 @@ struct mpde_problem {
   hipEvent_t ev() {
     if (pool_used == pool.size()) {
       hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      // no system-scope release on record: the timed kernels only touch device memory
+      if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
       pool.push_back(e);
     }
     return pool[pool_used++];
@@ -533,18 +534,21 @@ struct Solver {
     hipEvent_t pb = P->ev();
     if (!pb) return;
     (void)hipEventRecord(pb, st);
+    precord(kind, pa, pb, t, mode);
+    pa = nullptr;
+  }
+  void precord(int kind, hipEvent_t a, hipEvent_t b, const Table& t, int mode) {
     const double p = sizeof(TV), K = P->K;
     double per;
     if (kind == 2) {                                        // fused: no gamma round trip
-      if (mode == G_CHEB) per = (8 + K) * p;                // d, c, x, r, dinv in; x, r, d out
-      else if (mode == G_RESID) per = (6 + K) * p;          // u, c, b, dinv in; r, d out
+      if (mode == G_CHEB) per = (7 + K) * p;                // d, c, x, r, dinv in; x, r, d' out
+      else if (mode == G_RESID) per = (5 + K) * p;          // u, c, b, dinv in; r, d out
       else per = (2 + K) * p;                               // u, c in; y out
     } else if (kind == 0) per = (2 + K) * p;                // u, c in; gamma out
-    else if (mode == G_CHEB) per = (9 + K) * p;             // d, gamma, c, x, r, dinv in; x, r, d out
-    else if (mode == G_RESID) per = (7 + K) * p;            // u, gamma, c, b, dinv in; r, d out
+    else if (mode == G_CHEB) per = (8 + K) * p;             // d, gamma, c, x, r, dinv in; x, r, d' out
+    else if (mode == G_RESID) per = (6 + K) * p;            // u, gamma, c, b, dinv in; r, d out
     else per = (3 + K) * p;                                 // u, gamma, c in; y out
-    P->recs.push_back({kind, pa, pb, per * (double)t.npts});
-    pa = nullptr;
+    P->recs.push_back({kind, a, b, per * (double)t.npts});
   }
   void collect() {
     if (!P->opt.profile) return;
@@ -584,10 +588,11 @@ struct Solver {
     Level& L = P->lv[l];
     if (const FTab* f = fused(l, t)) {
       if constexpr (std::is_same<TV, float>::value && std::is_same<TC, float>::value) {
-        pbeg(l);
+        // timed launches carry their events in the dispatch itself
+        hipEvent_t e0 = prof(l) ? P->ev() : nullptr, e1 = prof(l) ? P->ev() : nullptr;
         launch_apply3<float, float, float>(st, f->d, f->nb(), f->g, L.d, P->ci, u, C(L.coef), mode, out, b, x, r, d,
-                                           V(L.dinv), cheb_step, partial);
-        pend(l, 2, t, mode);
+                                           V(L.dinv), cheb_step, partial, e0, e1);
+        if (e0 && e1) precord(2, e0, e1, t, mode);
       }
       return;
     }
@@ -598,6 +603,44 @@ struct Solver {
     launch_gather<TV, TV, TC>(D, st, t.d, t.nb(), L.d, P->ci, u, V(L.gam), C(L.coef), C(P->w), 0, mode, out, b, x,
                               r, d, V(L.dinv), cheb_step, partial);
     pend(l, 1, t, mode);
+  }
+
+  // `reps` back-to-back operator passes on level 0 in `mode`, between two
+  // events; mean microseconds per pass and algorithmic bytes per pass.
+  void time_operator(int mode, int reps, double& us, double& bytes) {
+    Level& L = P->lv[0];
+    const Table& t = L.all;
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    launch_hash_fill<TV>(st, t.d, t.nb(), L.d, V(L.dd), 777u);
+    launch_hash_fill<TV>(st, t.d, t.nb(), L.d, V(L.dd2), 778u);
+    launch_hash_fill<TV>(st, t.d, t.nb(), L.d, V(L.x), 779u);
+    launch_hash_fill<TV>(st, t.d, t.nb(), L.d, V(L.r), 780u);
+    auto one = [&](int k) {
+      TV* cur = V((k & 1) ? L.dd2 : L.dd);
+      TV* nxt = V((k & 1) ? L.dd : L.dd2);
+      if (mode == G_CHEB) op(0, t, cur, G_CHEB, nullptr, nullptr, V(L.x), V(L.r), nxt, k & 1, nullptr);
+      else if (mode == G_RESID) op(0, t, cur, G_RESID, nxt, V(L.x), nullptr, nullptr, V(L.r), 0, nullptr);
+      else op(0, t, cur, mode, nxt, nullptr, nullptr, nullptr, nullptr, 0, P->partial);
+    };
+    one(0);   // warm
+    HIPCHK(hipEventRecord(a, st));
+    for (int k = 0; k < reps; ++k) one(k);
+    HIPCHK(hipEventRecord(b, st));
+    HIPCHK(hipEventSynchronize(b));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    us = 1e3 * ms / reps;
+    const double p = sizeof(TV), K = P->K;
+    const bool f = fused(0, t) != nullptr;
+    // fused: as in precord(); two-pass: the gamma pass (2 + K) plus the gather
+    const double per = mode == G_CHEB ? (f ? 7 + K : 10 + 2 * K) * p
+                       : mode == G_RESID ? (f ? 5 + K : 8 + 2 * K) * p
+                                         : (f ? 2 + K : 5 + 2 * K) * p;
+    bytes = per * (double)t.npts;
   }
 
   // y = S u on level l for the instances of table t.
@@ -1630,6 +1673,30 @@ int mpde_autotune(mpde_problem* p, void* z, int32_t* chosen, double* best_ms) {
   }
   if (best_ms) *best_ms = best;
   return MPDE_OK;
+}
+
+int mpde_time_operator(mpde_problem* p, int32_t mode, int32_t reps, double* us_per_launch,
+                       double* bytes_per_launch) {
+  g_err.clear();
+  if (!p || !us_per_launch || !bytes_per_launch || mode < 0 || mode > 3 || reps < 1)
+    return fail(MPDE_ERR_INVALID_ARG, "mpde_time_operator: bad argument");
+  try {
+    double us = 0, bytes = 0;
+    if (p->dtype == MPDE_F32) {
+      Solver<float, float> S(p);
+      S.time_operator(mode, reps, us, bytes);
+    } else {
+      Solver<double, double> S(p);
+      S.time_operator(mode, reps, us, bytes);
+    }
+    *us_per_launch = us;
+    *bytes_per_launch = bytes;
+    return MPDE_OK;
+  } catch (const HipError& h) {
+    return hip_fail(h);
+  } catch (const std::string& m) {
+    return fail(MPDE_ERR_UNSUPPORTED, m);
+  }
 }
 
 int mpde_kernel_stats(const mpde_problem* p, mpde_kstat* out, int32_t max) {

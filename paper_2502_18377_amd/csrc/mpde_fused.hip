@@ -24,6 +24,9 @@
 // coefficients and of the mode vectors crosses HBM once per tile.
 #include "mpde_fused.hpp"
 
+#include <hip/hip_ext.h>
+
+#include <algorithm>
 #include <type_traits>
 
 namespace mpde {
@@ -532,49 +535,66 @@ __global__ void __launch_bounds__(kFThreads) k_apply3(const FTile* __restrict__ 
 template <typename TA, typename TV, typename TC, int M, int T>
 static void apply3_one(hipStream_t st, const FTile* tiles, int nb, FGeom g, const LInst* li, CIdx ci, const TV* u,
                        const TC* c, TV* out, const TV* bvec, TV* x, TV* r, TV* d, const TV* dinv, int cheb_step,
-                       double* partial, size_t lds) {
-  (void)hipFuncSetAttribute((const void*)k_apply3<TA, TV, TC, M, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds);
-  hipLaunchKernelGGL((k_apply3<TA, TV, TC, M, T>), dim3((unsigned)nb), dim3(kFThreads), lds, st, tiles, g, li, ci,
-                     u, c, out, bvec, x, r, d, dinv, cheb_step, partial);
+                       double* partial, size_t lds, hipEvent_t e0, hipEvent_t e1) {
+  // Raise the dynamic-LDS limit of this instantiation on the current device
+  // to the largest size requested so far (a host call, kept out of the
+  // per-launch path).
+  static size_t granted[64] = {};
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  dev = dev < 0 || dev >= 64 ? 0 : dev;
+  if (lds > granted[dev]) {
+    const size_t want = std::max<size_t>(lds, 96 * 1024);
+    (void)hipFuncSetAttribute((const void*)k_apply3<TA, TV, TC, M, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)want);
+    granted[dev] = want;
+  }
+  if (e0 && e1)   // timed: the events take the dispatch's own start and end times
+    hipExtLaunchKernelGGL((k_apply3<TA, TV, TC, M, T>), dim3((unsigned)nb), dim3(kFThreads), lds, st, e0, e1, 0,
+                          tiles, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial);
+  else
+    hipLaunchKernelGGL((k_apply3<TA, TV, TC, M, T>), dim3((unsigned)nb), dim3(kFThreads), lds, st, tiles, g, li, ci,
+                       u, c, out, bvec, x, r, d, dinv, cheb_step, partial);
 }
 
 template <typename TA, typename TV, typename TC, int M>
 static void apply3_mode(hipStream_t st, const FTile* tiles, int nb, FGeom g, const LInst* li, CIdx ci, const TV* u,
                         const TC* c, TV* out, const TV* bvec, TV* x, TV* r, TV* d, const TV* dinv, int cheb_step,
-                        double* partial, size_t lds) {
+                        double* partial, size_t lds, hipEvent_t e0, hipEvent_t e1) {
   // (the dot-product variant keeps the loop: unrolled, it spills)
   if (g.nt == 32 && M != G_STORE_DOT)
-    apply3_one<TA, TV, TC, M, M != G_STORE_DOT ? 32 : 0>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial, lds);
+    apply3_one<TA, TV, TC, M, M != G_STORE_DOT ? 32 : 0>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv,
+                                                         cheb_step, partial, lds, e0, e1);
   else
-    apply3_one<TA, TV, TC, M, 0>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial, lds);
+    apply3_one<TA, TV, TC, M, 0>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial, lds,
+                                 e0, e1);
 }
 
 template <typename TA, typename TV, typename TC>
 void launch_apply3(hipStream_t st, const FTile* tiles, int nb, FGeom g, const LInst* li, CIdx ci, const TV* u,
                    const TC* c, int mode, TV* out, const TV* bvec, TV* x, TV* r, TV* d, const TV* dinv,
-                   int cheb_step, double* partial) {
+                   int cheb_step, double* partial, hipEvent_t e0, hipEvent_t e1) {
   if (nb <= 0) return;
   const size_t lds = sizeof(TA) * (kFRing * (size_t)g.uplane + 16 * (size_t)g.qplane);   // qplane: float4 slots x 4
   switch (mode) {
     case G_STORE:
-      apply3_mode<TA, TV, TC, G_STORE>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial, lds);
+      apply3_mode<TA, TV, TC, G_STORE>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial, lds, e0, e1);
       break;
     case G_RESID:
-      apply3_mode<TA, TV, TC, G_RESID>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial, lds);
+      apply3_mode<TA, TV, TC, G_RESID>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial, lds, e0, e1);
       break;
     case G_CHEB:
-      apply3_mode<TA, TV, TC, G_CHEB>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial, lds);
+      apply3_mode<TA, TV, TC, G_CHEB>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial, lds, e0, e1);
       break;
     default:
       apply3_mode<TA, TV, TC, G_STORE_DOT>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial,
-                                           lds);
+                                           lds, e0, e1);
       break;
   }
 }
 
 template void launch_apply3<float, float, float>(hipStream_t, const FTile*, int, FGeom, const LInst*, CIdx,
                                                  const float*, const float*, int, float*, const float*, float*,
-                                                 float*, float*, const float*, int, double*);
+                                                 float*, float*, const float*, int, double*, hipEvent_t, hipEvent_t);
 
 }  // namespace mpde

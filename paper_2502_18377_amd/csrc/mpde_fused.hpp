@@ -70,10 +70,11 @@ __host__ __device__ inline FSpan fspan(int x0, int T, int n, int per) {
 
 // y = S u (no right-hand-side terms) with the epilogue of `mode`
 // (GatherMode); every instance of the tile table must have periodic x and y
-// axes and a non-periodic time axis of at least five points.
+// axes and a non-periodic time axis of at least five points.  With events
+// e0, e1 the launch records the dispatch's start and end time in them.
 template <typename TA, typename TV, typename TC>
 void launch_apply3(hipStream_t st, const FTile* tiles, int nb, FGeom g, const LInst* li, CIdx ci, const TV* u,
                    const TC* c, int mode, TV* out, const TV* bvec, TV* x, TV* r, TV* d, const TV* dinv,
-                   int cheb_step, double* partial);
+                   int cheb_step, double* partial, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 }  // namespace mpde

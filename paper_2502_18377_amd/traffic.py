@@ -10,12 +10,20 @@ WRITE_SIZE; both count KiB per dispatch):
     python -m paper_2502_18377_amd.traffic summarize D1 D2 OUT.json
 
 `run` performs a plain device-to-device copy of a known size (the
-calibration: counter KiB per copied byte), then one build + solve of the
-benchmark workload (64 instances of 32x64x64, FP32).  `summarize` averages
-the counters over the dispatches of the operator kernel on the finest grid
-(the launches the benchmark's roofline times), scales them by the copy's
-bytes-per-counter ratio and records the hash of the kernel source, so that
-bench.py reports the traffic only while the kernel is unchanged.
+calibration: counter KiB per copied byte), then what bench.py does: one
+build + solve of the benchmark workload (64 instances of 32x64x64, FP32)
+and the timing loops of the finest-grid operator (30 back-to-back passes
+per mode after one warm-up pass).  `summarize` averages the counters over
+the timing-loop dispatches of each mode (the launches the benchmark's
+roofline times), scales them by the copy's bytes-per-counter ratio and
+records the hash of the kernel source, so that bench.py reports the
+traffic only while the kernel is unchanged.
+
+    python -m paper_2502_18377_amd.traffic trace KERNEL_TRACE.csv > summary.txt
+
+summarises a `rocprofv3 --kernel-trace` run: per-kernel calls and average
+duration, and the same for the operator kernel's finest-grid dispatches
+(the largest grid among its launches), the set bench.py's roofline times.
 """
 import csv
 import glob
@@ -27,6 +35,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 256 << 20
 KERNELS = {"apply3": ("k_apply3", "mpde_fused.hip")}
+LOOP_MODES = (2, 1, 3)      # the modes bench.py times, in its order
+LOOP_REPS = 30
 
 
 def source_sha(fname):
@@ -52,6 +62,10 @@ def run():
     torch.cuda.synchronize()
     print("solve done", info["code"], float(info["iters"].mean()), flush=True)
     prob.close()
+    prob = Problem(pk["coeff"], pk["rhs"], pk["bc_values"], pk["shapes"], pk["steps"], pk["bc"], pk["mset"])
+    for mode in LOOP_MODES:
+        print("mode", mode, prob.time_operator(mode, reps=LOOP_REPS), flush=True)
+    prob.close()
 
 
 def _rows(d):
@@ -62,8 +76,15 @@ def _rows(d):
         return list(csv.DictReader(f))
 
 
+def _mode(kernel_name):
+    """Operator mode of a k_apply3 instantiation (its fourth template argument), -1 otherwise."""
+    if "k_apply3<" not in kernel_name:
+        return -1
+    return int(kernel_name.split("k_apply3<")[1].split(">")[0].split(",")[3])
+
+
 def _per_dispatch(rows, match):
-    """{dispatch id: (counter value summed over its rows, grid size)} for kernels containing `match`."""
+    """{dispatch id: (counter value summed over its rows, grid size, mode)} for kernels containing `match`."""
     out = {}
     for r in rows:
         if match not in r["Kernel_Name"]:
@@ -71,8 +92,8 @@ def _per_dispatch(rows, match):
         k = r["Dispatch_Id"]
         v = float(r["Counter_Value"])
         g = int(r.get("Grid_Size", r.get("Grid_Size_X", 0)) or 0)
-        prev = out.get(k, (0.0, g))
-        out[k] = (prev[0] + v, g)
+        prev = out.get(k, (0.0, g, _mode(r["Kernel_Name"])))
+        out[k] = (prev[0] + v, g, prev[2])
     return out
 
 
@@ -83,7 +104,7 @@ def summarize(d_fetch, d_write, out_path):
     for name, d in (("FETCH_SIZE", d_fetch), ("WRITE_SIZE", d_write)):
         rows = _rows(d)
         cp = _per_dispatch(rows, "copyBuffer")
-        big = [v for v, g in cp.values() if v > 0.5 * COPY_BYTES / 1024]
+        big = [v for v, g, _m in cp.values() if v > 0.5 * COPY_BYTES / 1024]
         if not big:
             raise SystemExit(f"{name}: no calibration copy dispatch found")
         kib = sum(big) / len(big)
@@ -94,17 +115,65 @@ def summarize(d_fetch, d_write, out_path):
             disp = _per_dispatch(rows, kname)
             if not disp:
                 continue
-            gmax = max(g for _, g in disp.values())
-            fin = [v for v, g in disp.values() if g == gmax]      # finest grid: the largest launches
-            ent = res["kernels"].setdefault(key, {"source_sha": source_sha(src), "finest_dispatches": len(fin)})
-            ent[f"{name}_KiB_per_dispatch"] = sum(fin) / len(fin)
-            ent[f"{name}_bytes_per_dispatch"] = sum(fin) / len(fin) * 1024.0 * scale[name]
+            gmax = max(g for _, g, _m in disp.values())
+            ent = res["kernels"].setdefault(key, {"source_sha": source_sha(src), "modes": {}})
+            for mode in sorted({m for _, _, m in disp.values()}):
+                # the timing loop: the last LOOP_REPS finest-grid dispatches of the mode
+                seq = [v for d, (v, g, m) in sorted(disp.items(), key=lambda kv: int(kv[0]))
+                       if g == gmax and m == mode]
+                fin = seq[-LOOP_REPS:]
+                if not fin:
+                    continue
+                e = ent["modes"].setdefault(str(mode), {"loop_dispatches": len(fin)})
+                e[f"{name}_KiB_per_dispatch"] = sum(fin) / len(fin)
+                e[f"{name}_bytes_per_dispatch"] = sum(fin) / len(fin) * 1024.0 * scale[name]
     for ent in res["kernels"].values():
-        if "FETCH_SIZE_bytes_per_dispatch" in ent and "WRITE_SIZE_bytes_per_dispatch" in ent:
-            ent["bytes_per_launch"] = ent["FETCH_SIZE_bytes_per_dispatch"] + ent["WRITE_SIZE_bytes_per_dispatch"]
+        for e in ent["modes"].values():
+            if "FETCH_SIZE_bytes_per_dispatch" in e and "WRITE_SIZE_bytes_per_dispatch" in e:
+                e["bytes_per_launch"] = e["FETCH_SIZE_bytes_per_dispatch"] + e["WRITE_SIZE_bytes_per_dispatch"]
     with open(out_path, "w") as f:
         json.dump(res, f, indent=1)
     print(json.dumps(res, indent=1))
+
+
+def trace(path):
+    with open(path) as f:
+        rows = list(csv.DictReader(f))
+    agg = {}
+    fin = {}
+    gmax = max((int(r.get("Grid_Size", r.get("Grid_Size_X", 0))) for r in rows if "k_apply3" in r["Kernel_Name"]), default=0)
+    for r in rows:
+        name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+        a = agg.setdefault(name, [0, 0.0])
+        a[0] += 1
+        a[1] += d
+        if "k_apply3" in name and int(r.get("Grid_Size", r.get("Grid_Size_X", 0))) == gmax:
+            b = fin.setdefault(name, [0, 0.0])
+            b[0] += 1
+            b[1] += d
+    tot = sum(v[1] for v in agg.values())
+    print(f"# total kernel time {tot / 1e3:.2f} ms")
+    print("kernel | calls | total_ms | avg_us | pct")
+    for k, (n, t) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        print(f"{k} | {n} | {t / 1e3:.2f} | {t / n:.2f} | {100 * t / tot:.2f}")
+    loops = {}
+    for r in rows:
+        name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+        if "k_apply3" in name and int(r.get("Grid_Size", r.get("Grid_Size_X", 0))) == gmax:
+            loops.setdefault(name, []).append((int(r["Dispatch_Id"]),
+                                               (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3))
+    print(f"# timing loops of bench.py (last {LOOP_REPS} finest-grid dispatches of each k_apply3 mode)")
+    for k, v in sorted(loops.items()):
+        d = [t for _, t in sorted(v)][-LOOP_REPS:]
+        print(f"{k} | {len(d)} | {sum(d) / 1e3:.2f} | {sum(d) / len(d):.2f}")
+    print(f"# finest-grid dispatches of k_apply3 (grid size {gmax}), whole run")
+    n_all = sum(v[0] for v in fin.values())
+    t_all = sum(v[1] for v in fin.values())
+    for k, (n, t) in sorted(fin.items()):
+        print(f"{k} | {n} | {t / 1e3:.2f} | {t / n:.2f}")
+    if n_all:
+        print(f"all modes | {n_all} | {t_all / 1e3:.2f} | {t_all / n_all:.2f}")
 
 
 if __name__ == "__main__":
@@ -112,5 +181,7 @@ if __name__ == "__main__":
         run()
     elif len(sys.argv) == 5 and sys.argv[1] == "summarize":
         summarize(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif len(sys.argv) == 3 and sys.argv[1] == "trace":
+        trace(sys.argv[2])
     else:
         raise SystemExit(__doc__)
