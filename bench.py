@@ -91,9 +91,11 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="also time every finest-grid operator launch of the solves with events (diagnostic; slows them)")
     ap.add_argument("--no-single", action="store_true", help="ragged: skip the one-problem-per-instance baseline")
-    ap.add_argument("--workload", choices=["rd2d", "ragged"], default="rd2d",
+    ap.add_argument("--workload", choices=["rd2d", "ragged", "learned", "adjoint"], default="rd2d",
                     help="rd2d: 64 x 32x64x64 reaction-diffusion (default); ragged: 256 ragged 1D+time instances, "
-                         "batched vs one problem per instance")
+                         "batched vs one problem per instance; learned: network trained on 32x64x64 systems, "
+                         "evaluated on held-out 64x128x128 instances against plain multigrid; adjoint: 32 x "
+                         "32x128x128 advection-diffusion, solve + adjoint gradient per step")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); instances of a batch are "
@@ -108,6 +110,10 @@ def main():
     dev = torch.device("cuda:0")
     if args.workload == "ragged":
         return bench_ragged(args, np, torch, W, Problem, pack, dev)
+    if args.workload == "learned":
+        return bench_learned(args, np, torch, W, Problem, pack, dev)
+    if args.workload == "adjoint":
+        return bench_adjoint(args, np, torch, W, Problem, pack, dev)
     B = args.batch
     insts = [W.reaction_diffusion_2d(i) for i in range(B)]
     pk = pack(insts, dtype=torch.float32, device=dev)
@@ -246,6 +252,125 @@ def bench_ragged(args, np, torch, W, Problem, pack, dev):
            {"value": round(single, 3), "unit": "solves/s", "mean_pcg_iters": round(float(np.mean(its1)), 2)},
            "batched_over_single": None if single is None else round(value / single, 2),
            "mean_pcg_iters": round(float(info["iters"].mean()), 2), "max_relres": float(info["relres"].max())}
+    print(json.dumps(out), flush=True)
+
+
+def bench_learned(args, np, torch, W, Problem, pack, dev):
+    """Learned-preconditioner form: a network trained on the GPU on systems
+    of the 32x64x64 reaction-diffusion generator (the correction at grid
+    level 1), evaluated on held-out instances at 64x128x128 (seeds from
+    10^6) solved to 1e-6 with flexible CG + learned correction against
+    plain multigrid-PCG on the same instances."""
+    from paper_2502_18377_amd.learned import Net, train
+    B = 128 if args.batch == 64 else args.batch
+    n_train, per_batch, steps = 8, 8, 300
+    probs = []
+    for k in range(n_train):
+        pk = pack([W.reaction_diffusion_2d(100 + per_batch * k + i) for i in range(per_batch)],
+                  dtype=torch.float32, device=dev)
+        probs.append(Problem(pk["coeff"], pk["rhs"], pk["bc_values"], pk["shapes"], pk["steps"], pk["bc"],
+                             pk["mset"]))
+    net = Net(2 + 6, seed=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = train(net, probs, 1, steps, lr=2e-3, lr_final=1e-4)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    for q in probs:
+        q.close()
+    loss = np.array([h[1] for h in hist])
+    plain = np.array([h[2] for h in hist])
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1),
+                             mp_context=multiprocessing.get_context("spawn")) as ex:
+        insts = list(ex.map(W.reaction_diffusion_2d_large, range(10**6, 10**6 + B)))
+    pk = pack(insts, dtype=torch.float32, device=dev)
+    del insts
+    prob = Problem(pk["coeff"], pk["rhs"], pk["bc_values"], pk["shapes"], pk["steps"], pk["bc"], pk["mset"])
+
+    def timed(reps):
+        z, info = prob.solve()               # warm
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            z, info = prob.solve()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps, info
+
+    reps = max(1, args.steps // 2)
+    t_plain, i_plain = timed(reps)
+    net.attach(prob, 1)
+    t_learn, i_learn = timed(reps)
+    Net.detach(prob)
+    prob.close()
+    for inf in (i_plain, i_learn):
+        if inf["code"] != 0:
+            raise SystemExit(f"solve did not converge: {inf}")
+    out = {"metric": METRIC, "value": round(B / t_learn, 3), "unit": "solves/s", "n_gpus": 1, "steps": reps,
+           "warmup": 1, "ms_per_step": round(t_learn * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{B} held-out instances of 2D-space+time reaction-diffusion, 64(t)x128x128 "
+                                  "periodic, FP32, solve to 1e-6; network trained on 32x64x64 systems",
+                      "batch": B, "grid": [64, 128, 128], "solver": "flexible CG + learned coarse correction"},
+           "plain_multigrid": {"value": round(B / t_plain, 3), "unit": "solves/s",
+                               "ms_per_solve_batch": round(t_plain * 1e3, 3),
+                               "mean_pcg_iters": round(float(i_plain["iters"].mean()), 2)},
+           "learned": {"mean_iters": round(float(i_learn["iters"].mean()), 2),
+                       "max_relres": float(i_learn["relres"].max())},
+           "learned_over_plain": round(t_plain / t_learn, 3),
+           "training": {"systems": n_train * per_batch, "steps": steps, "seconds": round(t_train, 2),
+                        "loss_first10": float(loss[:10].mean()), "loss_last10": float(loss[-10:].mean()),
+                        "plain_vcycle_loss_last10": float(plain[-10:].mean())}}
+    net.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_adjoint(args, np, torch, W, Problem, pack, dev):
+    """Differentiation form: 32 instances of the 2D+time advection-diffusion
+    workload at 32x128x128, FP32.  A step is build + forward solve + the
+    adjoint solve and gradients of the loss mean((u - target)^2) with
+    respect to the coefficient fields, the source and the boundary data."""
+    B = 32 if args.batch == 64 else args.batch
+    shape = (32, 128, 128)
+    pairs = [W.advection_diffusion_2d(i, shape=shape) for i in range(B)]
+    pk = pack([p[0] for p in pairs], dtype=torch.float32, device=dev)
+    N = int(np.prod(shape))
+    V = 7
+    target = torch.tensor(np.concatenate([p[1].ravel() for p in pairs]), dtype=torch.float32, device=dev)
+    del pairs
+
+    def step():
+        prob = Problem(pk["coeff"], pk["rhs"], pk["bc_values"], pk["shapes"], pk["steps"], pk["bc"], pk["mset"])
+        z, info = prob.solve()
+        zz = z.view(B, V, N)
+        u = zz[:, 0, :].reshape(-1)
+        g = torch.zeros_like(zz)
+        g[:, 0, :] = (2.0 / (B * N)) * (u - target).view(B, N)
+        gc, gf, gw, ainfo = prob.adjoint(g.reshape(-1))
+        prob.close()
+        return info, ainfo
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        info, ainfo = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    for inf in (info, ainfo):
+        if inf["code"] != 0:
+            raise SystemExit(f"solve did not converge: {inf}")
+    out = {"metric": METRIC, "value": round(B / dt, 3), "unit": "gradient solves/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{B} instances of 2D-space+time advection-diffusion, 32(t)x128x128 periodic, "
+                                  "FP32: build + solve + adjoint solve + gradients w.r.t. c, f, omega",
+                      "batch": B, "grid": list(shape)},
+           "forward_pcg_iters": round(float(info["iters"].mean()), 2),
+           "adjoint_pcg_iters": round(float(ainfo["iters"].mean()), 2),
+           "adjoint_max_relres": float(ainfo["relres"].max())}
     print(json.dumps(out), flush=True)
 
 

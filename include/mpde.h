@@ -82,7 +82,7 @@ typedef struct {
   int32_t nu;            /* smoothing steps before and after each coarse
                             correction (2) */
   int32_t coarse_min;    /* smallest coarsened periodic axis (8; axes go on
-                            to 4 while the coarsest grid would exceed 2048
+                            to 4 while the coarsest grid would exceed 4096
                             points); a non-periodic axis stops at >= 5 */
   int32_t check_every;   /* Krylov iterations between host convergence checks (2) */
   int32_t max_levels;    /* cap on grid levels including the finest (16) */

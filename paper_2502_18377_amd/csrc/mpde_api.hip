@@ -60,7 +60,7 @@ struct HipError {
     if (_e != hipSuccess) throw HipError{_e, #x};                   \
   } while (0)
 
-constexpr int kMaxDense = 2048;
+constexpr int kMaxDense = 4096;   // coarsest points per instance (block solves keep T*m doubles in LDS)
 
 // ---------------------------------------------------------------- stencils
 // 5-point weights from the moment conditions sum_k w_k o_k^p / p! = [p == q]

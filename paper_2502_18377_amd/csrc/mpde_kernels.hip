@@ -1603,7 +1603,7 @@ __global__ void __launch_bounds__(64) k_bb_solve16(const int* __restrict__ inst_
   const LInst& L = li[inst_list[blockIdx.x]];
   const int T = L.n[0], m = L.N / T;
   const long long base = L.doff;
-  __shared__ double ys[2048];           // y then x (T * m <= 2048, the dense-solve limit)
+  __shared__ double ys[4096];           // y then x (T * m <= 4096, the coarsest-grid limit)
   const int lane = threadIdx.x, r = lane >> 2, h = lane & 3;
   const bool live = r < m;
   const TV* B = bvec + L.voff;

@@ -96,10 +96,14 @@ def test_level_plan():
     inst = W.reaction_diffusion_1d_ragged(0, (24, 48))
     prob, zs, info = gpu_solve([inst], "f32")
     assert prob.levels(0) == [(24, 48), (24, 24), (24, 12), (24, 6)]
-    # a long time axis: periodic axes continue to 4 so the coarsest grid fits
+    # a long time axis: 64 x 8 x 8 = 4096 points still fits the coarsest solve
     inst = W.reaction_diffusion_2d(0, shape=(64, 32, 32))
     prob, zs, info = gpu_solve([inst], "f32")
-    assert prob.levels(0) == [(64, 32, 32), (64, 16, 16), (64, 8, 8), (64, 4, 4)]
+    assert prob.levels(0) == [(64, 32, 32), (64, 16, 16), (64, 8, 8)]
+    # a longer one: periodic axes continue to 4 so that the coarsest grid fits
+    inst = W.reaction_diffusion_2d(0, shape=(128, 16, 16))
+    prob, zs, info = gpu_solve([inst], "f32")
+    assert prob.levels(0) == [(128, 16, 16), (128, 8, 8), (128, 4, 4)]
 
 
 def test_nonfinite_input_rejected():
