@@ -30,6 +30,8 @@
 #include <cstring>
 #include <string>
 #include <type_traits>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "../../include/mpde.h"
@@ -89,13 +91,113 @@ void fd_table(int q, double out[5][5]) {
   }
 }
 
+// Device-memory cache.  Buffers a problem releases are kept per (device,
+// size) and handed to later builds, so that one-problem-per-batch use (build,
+// solve, free, repeated) pays hipMalloc/hipFree (about 0.1 ms per buffer,
+// ~160 buffers per problem) only once.  At most kCacheCap bytes per device
+// stay cached; a release beyond that, and every cached block when hipMalloc
+// runs out of memory, goes back to the runtime.  The cache lives until the
+// process ends.
+constexpr size_t kCacheCap = size_t(16) << 30;
+struct DevCache {
+  std::mutex mu;
+  std::map<std::pair<int, size_t>, std::vector<void*>> blocks;
+  std::map<int, size_t> bytes;
+  std::map<int, std::vector<hipStream_t>> streams;
+};
+DevCache& dcache() {
+  static DevCache* c = new DevCache();   // never destroyed: used until exit
+  return *c;
+}
+int cur_device() {
+  int d = 0;
+  (void)hipGetDevice(&d);
+  return d;
+}
+size_t cache_round(size_t b) { return (std::max<size_t>(b, 1) + 255) & ~size_t(255); }
+
+void* dev_get(size_t bytes) {
+  bytes = cache_round(bytes);
+  const int dev = cur_device();
+  DevCache& c = dcache();
+  {
+    std::lock_guard<std::mutex> g(c.mu);
+    auto it = c.blocks.find({dev, bytes});
+    if (it != c.blocks.end() && !it->second.empty()) {
+      void* p = it->second.back();
+      it->second.pop_back();
+      c.bytes[dev] -= bytes;
+      return p;
+    }
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e == hipErrorOutOfMemory) {   // give the cached blocks of this device back and retry
+    (void)hipGetLastError();
+    std::lock_guard<std::mutex> g(c.mu);
+    for (auto& kv : c.blocks)
+      if (kv.first.first == dev) {
+        for (void* q : kv.second) (void)hipFree(q);
+        kv.second.clear();
+      }
+    c.bytes[dev] = 0;
+    e = hipMalloc(&p, bytes);
+  }
+  if (e != hipSuccess) throw HipError{e, "hipMalloc"};
+  return p;
+}
+
+void dev_put(void* p, size_t bytes, int dev) {
+  if (!p) return;
+  bytes = cache_round(bytes);
+  DevCache& c = dcache();
+  std::lock_guard<std::mutex> g(c.mu);
+  if (c.bytes[dev] + bytes > kCacheCap) {
+    int keep = cur_device();
+    (void)hipSetDevice(dev);
+    (void)hipFree(p);
+    (void)hipSetDevice(keep);
+    return;
+  }
+  c.blocks[{dev, bytes}].push_back(p);
+  c.bytes[dev] += bytes;
+}
+
+// Streams for captured graphs, kept per device like the buffers.
+hipStream_t stream_get() {
+  const int dev = cur_device();
+  DevCache& c = dcache();
+  {
+    std::lock_guard<std::mutex> g(c.mu);
+    auto& v = c.streams[dev];
+    if (!v.empty()) {
+      hipStream_t s = v.back();
+      v.pop_back();
+      return s;
+    }
+  }
+  hipStream_t s = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e != hipSuccess) throw HipError{e, "hipStreamCreateWithFlags"};
+  return s;
+}
+void stream_put(hipStream_t s, int dev) {
+  if (!s) return;
+  DevCache& c = dcache();
+  std::lock_guard<std::mutex> g(c.mu);
+  c.streams[dev].push_back(s);
+}
+
+// A device buffer owned by a problem: returned to the cache on release.
+struct Block {
+  void* p;
+  size_t bytes;
+  int dev;
+};
+
 template <typename T>
 T* dalloc(size_t n) {
-  void* p = nullptr;
-  if (n == 0) n = 1;
-  hipError_t e = hipMalloc(&p, n * sizeof(T));
-  if (e != hipSuccess) throw HipError{e, "hipMalloc"};
-  return (T*)p;
+  return (T*)dev_get((n == 0 ? 1 : n) * sizeof(T));
 }
 
 // A host work table and its device copy, with per-instance block ranges.
@@ -217,18 +319,23 @@ struct mpde_problem {
     }
     return pool[pool_used++];
   }
-  std::vector<void*> owned;
+  std::vector<Block> owned;
+  int home = 0;                                            // device of the buffers and streams
   ~mpde_problem() {
     drop_graphs();
     for (hipEvent_t e : gev) if (e) (void)hipEventDestroy(e);
-    if (gst) (void)hipStreamDestroy(gst);
-    for (void* p : owned) (void)hipFree(p);
+    if (gst) {
+      (void)hipStreamSynchronize(gst);
+      stream_put(gst, home);
+    }
+    if (st) (void)hipStreamSynchronize(st);               // nothing in flight may still use a released buffer
+    for (const Block& b : owned) dev_put(b.p, b.bytes, b.dev);
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
   }
   template <typename T>
   T* alloc(size_t n) {
     T* p = dalloc<T>(n);
-    owned.push_back(p);
+    owned.push_back({p, (n == 0 ? 1 : n) * sizeof(T), cur_device()});
     return p;
   }
 };
@@ -714,7 +821,7 @@ struct Solver {
   void pcg_chunk_graph(int which, int chunk, double tol2) {
     const int key = (P->opt.nu * 1000 + chunk) * 2 + which;
     if (!P->gst) {
-      HIPCHK(hipStreamCreateWithFlags(&P->gst, hipStreamNonBlocking));
+      P->gst = stream_get();
       HIPCHK(hipEventCreateWithFlags(&P->gev[0], hipEventDisableTiming));
       HIPCHK(hipEventCreateWithFlags(&P->gev[1], hipEventDisableTiming));
     }
@@ -965,13 +1072,24 @@ struct Solver {
     double* GM = dalloc<double>(toty);
     double* Y = dalloc<double>(toty);
     int* dfail = dalloc<int>(B);
-    struct Free { std::vector<void*> v; ~Free() { for (void* p : v) (void)hipFree(p); } } fr{{LB, U, GM, Y, dfail}};
+    // temporaries go back to the cache after the probing (the stream is
+    // synchronised below before this scope ends)
+    const int dev = cur_device();
+    struct Free {
+      hipStream_t s;
+      std::vector<Block> v;
+      ~Free() {
+        (void)hipStreamSynchronize(s);
+        for (const Block& b : v) dev_put(b.p, b.bytes, b.dev);
+      }
+    } fr{st, {{LB, totb * sizeof(double), dev}, {U, toty * sizeof(double), dev}, {GM, toty * sizeof(double), dev},
+              {Y, toty * sizeof(double), dev}, {dfail, B * sizeof(int), dev}}};
     HIPCHK(hipMemsetAsync(LB, 0, totb * sizeof(double), st));
     HIPCHK(hipMemsetAsync(U, 0, toty * sizeof(double), st));
     HIPCHK(hipMemsetAsync(dfail, 0, B * sizeof(int), st));
     auto upload = [&](const void* h, size_t bytes) {
       void* d = dalloc<char>(bytes);
-      fr.v.push_back(d);
+      fr.v.push_back({d, bytes, dev});
       HIPCHK(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, st));
       return d;
     };
@@ -1384,6 +1502,7 @@ int mpde_build(const mpde_desc* d, mpde_problem** out) {
   if (!P) return fail(MPDE_ERR_OUT_OF_MEMORY, "host allocation failed");
   P->dtype = d->dtype; P->D = d->ndim; P->B = d->batch; P->V = 1 + 2 * d->ndim;
   P->mset = d->mset; P->opt = opt; P->st = (hipStream_t)d->stream;
+  P->home = cur_device();
   for (int a = 0; a < 3; ++a) { P->bc_lo[a] = d->bc_lo[a]; P->bc_hi[a] = d->bc_hi[a]; }
   int K = 0;
   for (int v = 0; v < 1 + 2 * kMaxD; ++v) P->ci.k[v] = -1;
