@@ -310,7 +310,7 @@ __global__ void __launch_bounds__(kFThreads) k_apply3(const FTile* __restrict__ 
     chB = (TA)(2.0 * rn / de);
   }
   const TA ith = (TA)(1.0 / L.cheb_theta);
-  double dot = 0;
+  TA dot = 0;   // per-thread u.y over at most a few dozen planes; the block sum is FP64
 
   // Epilogue inputs of plane j (x, r, dinv for a Chebyshev step; b, dinv for
   // a residual), loaded one plane before the epilogue runs.
@@ -339,7 +339,7 @@ __global__ void __launch_bounds__(kFThreads) k_apply3(const FTile* __restrict__ 
       bst(rOut, o, pj, y);
     } else if (MODE == G_STORE_DOT) {
       bst(rOut, o, pj, y);
-      if (o != kOOB) dot += (double)uj * (double)y;
+      if (o != kOOB) dot += uj * y;
     } else if (MODE == G_RESID) {
       const TA r = e[0] - y;
       bst(rOut, o, pj, r);
@@ -527,7 +527,7 @@ __global__ void __launch_bounds__(kFThreads) k_apply3(const FTile* __restrict__ 
     step(p + 1, I1(), I4());
   }
   if (MODE == G_STORE_DOT) {
-    const double sdot = fblock_sum<TA>(dot);
+    const double sdot = fblock_sum<TA>((double)dot);
     if (threadIdx.x == 0) partial[tl.pad] = sdot;
   }
 }
@@ -561,9 +561,8 @@ template <typename TA, typename TV, typename TC, int M>
 static void apply3_mode(hipStream_t st, const FTile* tiles, int nb, FGeom g, const LInst* li, CIdx ci, const TV* u,
                         const TC* c, TV* out, const TV* bvec, TV* x, TV* r, TV* d, const TV* dinv, int cheb_step,
                         double* partial, size_t lds, hipEvent_t e0, hipEvent_t e1) {
-  // (the dot-product variant keeps the loop: unrolled, it spills)
-  if (g.nt == 32 && M != G_STORE_DOT)
-    apply3_one<TA, TV, TC, M, M != G_STORE_DOT ? 32 : 0>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv,
+  if (g.nt == 32)
+    apply3_one<TA, TV, TC, M, 32>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv,
                                                          cheb_step, partial, lds, e0, e1);
   else
     apply3_one<TA, TV, TC, M, 0>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial, lds,
