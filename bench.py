@@ -157,10 +157,11 @@ def main():
     # over back-to-back launches with HIP events on the library's stream.
     prob = Problem(pk["coeff"], pk["rhs"], pk["bc_values"], pk["shapes"], pk["steps"], pk["bc"], pk["mset"])
     modes = {}
-    for mode, label in ((2, "chebyshev"), (1, "residual"), (3, "apply_dot")):
+    for mode, label in ((2, "chebyshev"), (1, "residual"), (3, "apply_dot"), (4, "residual_fp64")):
         us, by = prob.time_operator(mode, reps=30)
         modes[label] = {"us_per_launch": round(us, 2), "bytes_per_launch": by,
-                        "GB/s": round(by / (us * 1e-6) / 1e9, 1)}
+                        "GB/s": round(by / (us * 1e-6) / 1e9, 1),
+                        "traffic": traffic_for("apply3", mode)}
     prob.close()
     ch = modes["chebyshev"]
     achieved = ch["bytes_per_launch"] / (ch["us_per_launch"] * 1e-6) / 1e9

@@ -187,13 +187,17 @@ int mpde_kernel_stats(const mpde_problem *p, mpde_kstat *out, int32_t max);
 /* Timing of the finest-grid operator pass (the matrix-free normal-equation
  * operator of Eq. 9 in reduced form, fused with the epilogue `mode`: 0 y = S u,
  * 1 residual, 2 Chebyshev smoothing step, 3 y = S u with per-block u.y
- * partial sums): `reps` launches back to back on the problem's stream on the
- * library's own level-0 work vectors, between two HIP events.  Writes the
- * mean duration per launch in microseconds and the algorithmic HBM bytes of
- * one launch (inputs read once, outputs written once).  Overwrites only
- * library scratch vectors: a later mpde_solve or mpde_solve_adjoint is
- * unaffected.  Returns MPDE_ERR_INVALID_ARG for a NULL problem or output,
- * mode outside 0..3 or reps < 1. */
+ * partial sums, 4 the FP64 residual r = b - S u of the outer refinement, in
+ * FP64 arithmetic on FP64 vectors): `reps` launches back to back on the
+ * problem's stream on the library's own level-0 work vectors, between two HIP
+ * events.  Writes the mean duration per launch in microseconds and the
+ * algorithmic HBM bytes of one launch (inputs read once, outputs written
+ * once).  Overwrites only library scratch vectors: a later mpde_solve or
+ * mpde_solve_adjoint is unaffected.  Returns MPDE_ERR_INVALID_ARG for a NULL
+ * problem or output, mode outside 0..4 or reps < 1, and
+ * MPDE_ERR_UNSUPPORTED for mode 4 on a problem without a fused FP64 pass
+ * (FP64 coefficients, fused operator off, or a level shape it does not
+ * cover). */
 int mpde_time_operator(mpde_problem *p, int32_t mode, int32_t reps, double *us_per_launch,
                        double *bytes_per_launch);
 

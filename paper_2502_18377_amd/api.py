@@ -137,7 +137,8 @@ class Problem:
     def time_operator(self, mode=2, reps=20):
         """Mean microseconds and algorithmic HBM bytes of one finest-grid
         operator pass in `mode` (0 apply, 1 residual, 2 Chebyshev step, 3
-        apply with dot products), timed over `reps` back-to-back passes."""
+        apply with dot products, 4 the FP64 residual of the outer
+        refinement), timed over `reps` back-to-back passes."""
         us, by = ctypes.c_double(), ctypes.c_double()
         N.check(self._lib.mpde_time_operator(self._h, mode, reps, ctypes.byref(us), ctypes.byref(by)))
         return us.value, by.value

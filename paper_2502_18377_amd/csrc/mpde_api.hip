@@ -228,6 +228,7 @@ struct Level {
   long long npts = 0;          // total points of this level
   Table all, smooth, dense;    // all instances / non-coarsest / coarsest (rows)
   FTab fall, fsmooth;          // fused-operator tiles for `all` and `smooth`
+  FTab fall64;                 // level 0, FP64 arithmetic (outer residual)
   std::vector<int> cinst64, cinst16, cinstg;   // coarsest here: 64-point / <= 16-point / other planes
   int *d_cinst64 = nullptr, *d_cinst16 = nullptr, *d_cinstg = nullptr;
   void* coef = nullptr;        // TC [K planes per instance]
@@ -281,6 +282,7 @@ struct mpde_problem {
   long long* zoff = nullptr;
   void *f = nullptr, *w = nullptr;                          // TC, level-0 layout
   double *u64 = nullptr, *r64 = nullptr, *g64 = nullptr, *ghat = nullptr, *vloc = nullptr, *du64 = nullptr;
+  double* rhs64 = nullptr;   // forward right side A_u^T Pi d on level 0 (the residual at u = 0)
   void *e = nullptr, *rk = nullptr, *zk = nullptr, *pk = nullptr, *qk = nullptr;   // TV, level 0
   double* partial = nullptr;
   double *rz_new = nullptr, *rz = nullptr, *beta = nullptr, *pq = nullptr, *alpha = nullptr, *rn2 = nullptr,
@@ -364,13 +366,18 @@ void make_table(Table& t, const std::vector<LInst>& h, int B, const std::vector<
 }
 
 // Tiles of the fused operator: each selected instance is cut into (TX, TY)
-// tiles of its (x, y) plane; TX and TY are common to the level and chosen so
-// that the rows of a tile plus halo fit one block (kFThreads points) and the
-// level has at least ~2 blocks per compute unit where the shapes allow.
-// Consecutive groups of 8 instances are interleaved tile by tile, so that
-// with round-robin block dispatch all tiles of one instance (which share
-// halos) run on the same XCD and its L2.
-void make_ftab(FTab& f, const std::vector<LInst>& h, int B, const std::vector<int>& sel, int D) {
+// tiles of its (x, y) plane; TX and TY are divisors of the largest extents,
+// common to the level, such that the rows of a tile plus halo fit one block
+// of `nth` threads (one row point each) and its staged u plane fits two
+// values per thread.  Among those, the level gets at least 512 blocks (two
+// per compute unit) where the shapes allow, and then the fewest wavefronts
+// in total: halo rows are evaluated by every tile that needs them, so this
+// minimises the redundant row work.  `esize` is the byte size of the
+// arithmetic type (LDS budget).  Consecutive groups of 8 instances are
+// interleaved tile by tile, so that with round-robin block dispatch all
+// tiles of one instance (which share halos) run on the same XCD and its L2.
+void make_ftab(FTab& f, const std::vector<LInst>& h, int B, const std::vector<int>& sel, int D, int nth,
+               size_t esize) {
   f.h.clear();
   f.bstart.assign(B + 1, 0);
   f.ok = false;
@@ -380,41 +387,61 @@ void make_ftab(FTab& f, const std::vector<LInst>& h, int B, const std::vector<in
     if (!sel[b] || h[b].N == 0) continue;
     const LInst& q = h[b];
     if (q.per[0] || !q.per[1] || !q.per[2] || q.n[0] < 5 || q.n[1] < 4 || q.n[2] < 4) return;
-    if (4LL * q.N * 7 >= (1LL << 31)) return;   // buffer offsets of the kernel are 31-bit
+    if (4LL * q.N * 7 >= (1LL << 31) || (long long)esize * q.N >= (1LL << 31)) return;   // 31-bit buffer offsets
     ++nsel;
     mnx = std::max(mnx, q.n[1]);
     mny = std::max(mny, q.n[2]);
   }
   if (nsel == 0) return;
-  auto fits = [&](int TX, int TY) {
+  // tiles of shape (TX, TY): count, total wavefronts, LDS extents; false if
+  // some tile does not fit a block
+  struct Cut {
+    long long tiles = 0, waves = 0;
+    int uplane = 0, qplane = 0;
+  };
+  auto cut = [&](int TX, int TY, Cut& c) {
+    c = Cut{};
     for (int b = 0; b < B; ++b) {
       if (!sel[b] || h[b].N == 0) continue;
       const LInst& q = h[b];
       for (int x0 = 0; x0 < q.n[1]; x0 += TX)
         for (int y0 = 0; y0 < q.n[2]; y0 += TY) {
           const FSpan X = fspan(x0, TX, q.n[1], 1), Y = fspan(y0, TY, q.n[2], 1);
-          if (X.qn * Y.qn > kFThreads || X.un * Y.un > 2 * kFThreads) return false;
+          if (X.qn * Y.qn > nth || X.un * Y.un > 2 * nth) return false;
+          c.tiles += 1;
+          c.waves += (X.qn * Y.qn + 63) / 64;
+          c.uplane = std::max(c.uplane, X.un * Y.un);
+          c.qplane = std::max(c.qplane, X.qs * Y.qs);
         }
     }
-    return true;
+    c.uplane = (c.uplane + 1 + 3) & ~3;   // spare slot for idle threads' staging writes; 16-byte rows
+    return esize * (kFRing * (size_t)c.uplane + 16 * (size_t)c.qplane) <= 160000;   // LDS per block
   };
-  auto count = [&](int TX, int TY) {
-    long long n = 0;
-    for (int b = 0; b < B; ++b)
-      if (sel[b] && h[b].N > 0) n += (long long)((h[b].n[1] + TX - 1) / TX) * ((h[b].n[2] + TY - 1) / TY);
-    return n;
-  };
-  int TY = std::min(mny, 64), TX = 0;
-  for (;; TY = std::max(1, TY / 2)) {
-    for (int t = mnx; t >= 1; --t)
-      if (mnx % t == 0 && fits(t, TY)) { TX = t; break; }
-    if (TX > 0 || TY == 1) break;
+  std::vector<std::pair<int, int>> cand;   // larger tiles first (preferred on ties)
+  for (int ty = mny; ty >= std::min(4, mny); --ty)
+    if (mny % ty == 0)
+      for (int tx = mnx; tx >= std::min(4, mnx); --tx)
+        if (mnx % tx == 0) cand.push_back({tx, ty});
+  long long most = 0;
+  std::vector<std::pair<std::pair<int, int>, Cut>> ok;
+  for (auto& tt : cand) {
+    Cut c;
+    if (!cut(tt.first, tt.second, c)) continue;
+    ok.push_back({tt, c});
+    most = std::max(most, c.tiles);
   }
-  if (TX == 0) return;
-  while (count(TX, TY) < 512 && TX % 2 == 0 && TX / 2 >= 4 && fits(TX / 2, TY)) TX /= 2;
+  if (ok.empty()) return;
+  const long long want = std::min<long long>(512, most);
+  int bi = -1;
+  for (int i = 0; i < (int)ok.size(); ++i) {
+    if (ok[i].second.tiles < want) continue;
+    if (bi < 0 || ok[i].second.waves < ok[bi].second.waves) bi = i;
+  }
+  const int TX = ok[bi].first.first, TY = ok[bi].first.second;
   f.g.TX = TX;
   f.g.TY = TY;
-  f.g.uplane = f.g.qplane = 0;
+  f.g.uplane = ok[bi].second.uplane;
+  f.g.qplane = ok[bi].second.qplane;
   f.g.nt = -1;
   std::vector<std::vector<FTile>> per(B);
   int slot = 0;
@@ -424,16 +451,11 @@ void make_ftab(FTab& f, const std::vector<LInst>& h, int B, const std::vector<in
     const LInst& q = h[b];
     for (int x0 = 0; x0 < q.n[1]; x0 += TX)
       for (int y0 = 0; y0 < q.n[2]; y0 += TY) {
-        const FSpan X = fspan(x0, TX, q.n[1], 1), Y = fspan(y0, TY, q.n[2], 1);
-        f.g.uplane = std::max(f.g.uplane, X.un * Y.un);
-        f.g.qplane = std::max(f.g.qplane, X.qs * Y.qs);
         per[b].push_back(FTile{b, x0, y0, slot++});
         f.g.nt = (f.g.nt == -1 || f.g.nt == q.n[0]) ? q.n[0] : 0;
       }
   }
   f.bstart[B] = slot;
-  f.g.uplane = (f.g.uplane + 1 + 3) & ~3;   // spare slot for idle threads' staging writes; 16-byte rows
-  if (sizeof(float) * (kFRing * (size_t)f.g.uplane + 16 * (size_t)f.g.qplane) > 160000) return;   // LDS per block
   for (int g0 = 0; g0 < B; g0 += 8) {
     size_t mt = 0;
     for (int b = g0; b < std::min(B, g0 + 8); ++b) mt = std::max(mt, per[b].size());
@@ -724,10 +746,22 @@ struct Solver {
     launch_hash_fill<TV>(st, t.d, t.nb(), L.d, V(L.dd2), 778u);
     launch_hash_fill<TV>(st, t.d, t.nb(), L.d, V(L.x), 779u);
     launch_hash_fill<TV>(st, t.d, t.nb(), L.d, V(L.r), 780u);
+    // mode 4: the FP64 residual pass of the outer refinement
+    const FTab& f64 = L.fall64;
+    if (mode == 4) {
+      if (!std::is_same<TC, float>::value || !P->opt.fused || !f64.ok)
+        throw std::string("time_operator: this problem has no fused FP64 residual pass");
+      launch_hash_fill<double>(st, t.d, t.nb(), L.d, P->u64, 781u);
+      launch_hash_fill<double>(st, t.d, t.nb(), L.d, P->rhs64, 782u);
+    }
     auto one = [&](int k) {
       TV* cur = V((k & 1) ? L.dd2 : L.dd);
       TV* nxt = V((k & 1) ? L.dd : L.dd2);
-      if (mode == G_CHEB) op(0, t, cur, G_CHEB, nullptr, nullptr, V(L.x), V(L.r), nxt, k & 1, nullptr);
+      if (mode == 4) {
+        if constexpr (std::is_same<TC, float>::value)
+          launch_apply3<double, double, float>(st, f64.d, f64.nb(), f64.g, L.d, P->ci, P->u64, C(L.coef), G_RESID,
+                                               P->r64, P->rhs64, nullptr, nullptr, nullptr, nullptr, 0, nullptr);
+      } else if (mode == G_CHEB) op(0, t, cur, G_CHEB, nullptr, nullptr, V(L.x), V(L.r), nxt, k & 1, nullptr);
       else if (mode == G_RESID) op(0, t, cur, G_RESID, nxt, V(L.x), nullptr, nullptr, V(L.r), 0, nullptr);
       else op(0, t, cur, mode, nxt, nullptr, nullptr, nullptr, nullptr, 0, P->partial);
     };
@@ -744,7 +778,9 @@ struct Solver {
     const double p = sizeof(TV), K = P->K;
     const bool f = fused(0, t) != nullptr;
     // fused: as in precord(); two-pass: the gamma pass (2 + K) plus the gather
-    const double per = mode == G_CHEB ? (f ? 7 + K : 10 + 2 * K) * p
+    // mode 4: u, rhs, r in FP64 and the FP32 coefficients
+    const double per = mode == 4 ? 24 + 4 * K
+                       : mode == G_CHEB ? (f ? 7 + K : 10 + 2 * K) * p
                        : mode == G_RESID ? (f ? 5 + K : 8 + 2 * K) * p
                                          : (f ? 2 + K : 5 + 2 * K) * p;
     bytes = per * (double)t.npts;
@@ -945,14 +981,32 @@ struct Solver {
 
   // FP64 residual r64 = rhs - S u64 on level 0, and ||r64||^2 per instance
   // into rn2 (adjoint: rhs = ghat, sigma = 0; forward: sigma = 1, rhs = g).
-  void residual64(bool adjoint, double* u64) {
+  // The forward right side A_u^T Pi d is the residual at u = 0: the first
+  // residual of a solve (zero_u) evaluates it with the right-side terms and
+  // keeps it in rhs64; later ones, and every adjoint one, are one fused FP64
+  // pass r = rhs - S u where the level has a fused tile table.
+  void residual64(bool adjoint, double* u64, bool zero_u) {
     Level& L0 = P->lv[0];
     const Table& t = L0.all;
-    launch_gamma<double, double, TC>(D, st, t.d, t.nb(), L0.d, P->ci, u64, C(L0.coef), C(P->f), adjoint ? 0 : 1,
-                                     P->g64);
-    launch_gather<double, double, TC>(D, st, t.d, t.nb(), L0.d, P->ci, u64, P->g64, C(L0.coef), C(P->w),
-                                      adjoint ? 0 : 1, G_RESID, P->r64, adjoint ? P->ghat : nullptr, nullptr,
-                                      nullptr, nullptr, nullptr, 0, nullptr);
+    const FTab& f = L0.fall64;
+    bool done = false;
+    if constexpr (std::is_same<TC, float>::value) {
+      if (P->opt.fused && f.ok && (adjoint || !zero_u)) {
+        launch_apply3<double, double, float>(st, f.d, f.nb(), f.g, L0.d, P->ci, u64, C(L0.coef), G_RESID, P->r64,
+                                             adjoint ? P->ghat : P->rhs64, nullptr, nullptr, nullptr, nullptr, 0,
+                                             nullptr);
+        done = true;
+      }
+    }
+    if (!done) {
+      launch_gamma<double, double, TC>(D, st, t.d, t.nb(), L0.d, P->ci, u64, C(L0.coef), C(P->f), adjoint ? 0 : 1,
+                                       P->g64);
+      launch_gather<double, double, TC>(D, st, t.d, t.nb(), L0.d, P->ci, u64, P->g64, C(L0.coef), C(P->w),
+                                        adjoint ? 0 : 1, G_RESID, P->r64, adjoint ? P->ghat : nullptr, nullptr,
+                                        nullptr, nullptr, nullptr, 0, nullptr);
+      if (!adjoint && zero_u)
+        HIPCHK(hipMemcpyAsync(P->rhs64, P->r64, (size_t)L0.npts * sizeof(double), hipMemcpyDeviceToDevice, st));
+    }
     launch_dot<double, double>(st, t.d, t.nb(), L0.d, P->r64, P->r64, P->partial);
     finish(t, P->rn2);
   }
@@ -972,7 +1026,7 @@ struct Solver {
     std::vector<int> act(B);
     int code = MPDE_WARN_NOT_CONVERGED;
     for (int k = 0; k <= P->opt.max_outer; ++k) {
-      residual64(adjoint, u64);
+      residual64(adjoint, u64, k == 0);
       HIPCHK(hipMemcpyAsync(rn.data(), P->rn2, B * sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       bool all = true;
@@ -1065,6 +1119,7 @@ struct Solver {
       Tn[b] = q.n[0];
       mn[b] = q.N / q.n[0];
       boff[b] = totb; totb += (long long)Tn[b] * 5 * mn[b] * mn[b];
+      totb = (totb + 3) & ~3LL;   // 16-byte aligned rows for the vector loads of the solve
       yoff[b] = toty; toty += (long long)std::min(q.n[0], NCOL) * mn[b] * q.N;
     }
     double* LB = dalloc<double>(totb);
@@ -1357,6 +1412,21 @@ void build_impl(mpde_problem* P, const mpde_desc* d) {
           q.gi[a][cls][1] = -g12 / det;
           q.gi[a][cls][2] = g11 / det;
         }
+        float* fk = q.fk[a];
+        fk[FK_A] = (float)(q.wT[a] * q.wT[a]);
+        fk[FK_AH] = (float)(0.5 * q.wT[a] * q.wT[a]);
+        fk[FK_B1] = (float)(q.wC1[a] * q.wC1[a]);
+        fk[FK_B2] = (float)(q.wC2[a] * q.wC2[a]);
+        fk[FK_B1D] = (float)(q.wC1[a] * q.wC1[a] / 12.0);
+        fk[FK_B2D] = (float)(q.wC2[a] * q.wC2[a] / 12.0);
+        fk[FK_S1] = (float)q.is1[a];
+        fk[FK_S2] = (float)q.is2[a];
+        fk[FK_G0] = (float)q.gi[a][0][0];
+        fk[FK_G0 + 1] = (float)q.gi[a][0][2];
+        for (int k = 0; k < 3; ++k) {
+          fk[FK_G1 + k] = (float)q.gi[a][1][k];
+          fk[FK_G2 + k] = (float)q.gi[a][2][k];
+        }
       }
       q.N = (int)N;
       q.coarsest = (l == P->nlev[b] - 1);
@@ -1375,8 +1445,9 @@ void build_impl(mpde_problem* P, const mpde_desc* d) {
     make_table(L.all, L.h, B, sel_all);
     make_table(L.smooth, L.h, B, sel_smooth);
     make_table(L.dense, L.h, B, sel_dense);
-    make_ftab(L.fall, L.h, B, sel_all, D);
-    make_ftab(L.fsmooth, L.h, B, sel_smooth, D);
+    make_ftab(L.fall, L.h, B, sel_all, D, kFThreads, sizeof(float));
+    make_ftab(L.fsmooth, L.h, B, sel_smooth, D, kFThreads, sizeof(float));
+    if (l == 0) make_ftab(L.fall64, L.h, B, sel_all, D, kFThreads64, sizeof(double));
   }
   // device structures
   size_t maxnb = 1;
@@ -1384,9 +1455,10 @@ void build_impl(mpde_problem* P, const mpde_desc* d) {
     L.d = P->alloc<LInst>(B);
     HIPCHK(hipMemcpy(L.d, L.h.data(), B * sizeof(LInst), hipMemcpyHostToDevice));
     upload_table(P, L.all); upload_table(P, L.smooth); upload_table(P, L.dense);
-    upload_ftab(P, L.fall); upload_ftab(P, L.fsmooth);
+    upload_ftab(P, L.fall); upload_ftab(P, L.fsmooth); upload_ftab(P, L.fall64);
     maxnb = std::max(maxnb, L.all.h.size());
     maxnb = std::max(maxnb, (size_t)L.fall.bstart.back());
+    if (!L.fall64.bstart.empty()) maxnb = std::max(maxnb, (size_t)L.fall64.bstart.back());   // level 0 only
   }
   S.alloc_vectors();
   const long long n0 = P->lv[0].npts;
@@ -1400,6 +1472,7 @@ void build_impl(mpde_problem* P, const mpde_desc* d) {
   P->u64 = P->alloc<double>(n0);
   P->du64 = P->alloc<double>(n0);
   P->r64 = P->alloc<double>(n0);
+  P->rhs64 = P->alloc<double>(n0);
   P->g64 = P->alloc<double>(n0);
   P->ghat = P->alloc<double>(n0);
   P->vloc = P->alloc<double>((size_t)2 * D * n0);
@@ -1797,7 +1870,7 @@ int mpde_autotune(mpde_problem* p, void* z, int32_t* chosen, double* best_ms) {
 int mpde_time_operator(mpde_problem* p, int32_t mode, int32_t reps, double* us_per_launch,
                        double* bytes_per_launch) {
   g_err.clear();
-  if (!p || !us_per_launch || !bytes_per_launch || mode < 0 || mode > 3 || reps < 1)
+  if (!p || !us_per_launch || !bytes_per_launch || mode < 0 || mode > 4 || reps < 1)
     return fail(MPDE_ERR_INVALID_ARG, "mpde_time_operator: bad argument");
   try {
     double us = 0, bytes = 0;

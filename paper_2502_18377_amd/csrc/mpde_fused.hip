@@ -73,18 +73,33 @@ constexpr int kFMaxU = 2;   // staged u values per thread and plane
 
 __device__ __forceinline__ int fwrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
+__device__ __forceinline__ float fm(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fm(double a, double b, double c) { return fma(a, b, c); }
+// gamma = num / kappa with kappa >= 1: in FP32 the hardware reciprocal
+// (1 ulp) is accurate to rounding; FP64 divides exactly.
+__device__ __forceinline__ float fdivk(float n, float k) { return n * __builtin_amdgcn_rcpf(k); }
+__device__ __forceinline__ double fdivk(double n, double k) { return n / k; }
+
 // Raw buffer access: the resource (base, size) and the uniform byte offset
 // live in scalar registers, the per-thread byte offset in one vector
 // register, so a load costs no vector address arithmetic.
 using brsrc = __amdgpu_buffer_rsrc_t;
+typedef unsigned int fu2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ brsrc mkbuf(const void* p, long long bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
-__device__ __forceinline__ float bld(brsrc r, unsigned voff, unsigned soff) {
+template <typename T> __device__ __forceinline__ T bld(brsrc r, unsigned voff, unsigned soff);
+template <> __device__ __forceinline__ float bld<float>(brsrc r, unsigned voff, unsigned soff) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+template <> __device__ __forceinline__ double bld<double>(brsrc r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
 }
 __device__ __forceinline__ void bst(brsrc r, unsigned voff, unsigned soff, float v) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void bst(brsrc r, unsigned voff, unsigned soff, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(fu2, v), r, (int)voff, (int)soff, 0);
 }
 // A per-thread offset past the end of every buffer the kernel uses (their
 // sizes are below 2^31 bytes, checked by the host, and offset + plane offset
@@ -93,6 +108,40 @@ __device__ __forceinline__ void bst(brsrc r, unsigned voff, unsigned soff, float
 // that every memory instruction of the plane loop is issued unconditionally
 // and the compiler's wait counts stay exact across loop iterations.
 constexpr unsigned kOOB = 0x80000000u;
+
+// One staged row-value slot (C1, C2, T+, T-) in the arithmetic type.
+struct __align__(16) FSlotD {
+  double x, y, z, w;
+};
+template <typename TA> struct FSlot;
+template <> struct FSlot<float> {
+  using type = float4;
+  static __device__ __forceinline__ float4 make(float a, float b, float c, float d) { return make_float4(a, b, c, d); }
+};
+template <> struct FSlot<double> {
+  using type = FSlotD;
+  static __device__ __forceinline__ FSlotD make(double a, double b, double c, double d) { return FSlotD{a, b, c, d}; }
+};
+
+// Per-axis constant FK_* of the fused operator: the host's FP32 copy, or
+// the same quantity formed in FP64 from the FP64 level data.
+template <typename TA> __device__ __forceinline__ TA fkc(const LInst& L, int a, int i);
+template <> __device__ __forceinline__ float fkc<float>(const LInst& L, int a, int i) { return L.fk[a][i]; }
+template <> __device__ __forceinline__ double fkc<double>(const LInst& L, int a, int i) {
+  switch (i) {
+    case FK_A: return L.wT[a] * L.wT[a];
+    case FK_AH: return 0.5 * L.wT[a] * L.wT[a];
+    case FK_B1: return L.wC1[a] * L.wC1[a];
+    case FK_B2: return L.wC2[a] * L.wC2[a];
+    case FK_S1: return L.is1[a];
+    case FK_S2: return L.is2[a];
+    case FK_G0: return L.gi[a][0][0];
+    case FK_G0 + 1: return L.gi[a][0][2];
+    case FK_B1D: return L.wC1[a] * L.wC1[a] / 12.0;
+    case FK_B2D: return L.wC2[a] * L.wC2[a] / 12.0;
+    default: return i < FK_G2 ? L.gi[a][1][i - FK_G1] : L.gi[a][2][i - FK_G2];
+  }
+}
 
 // Difference sums of the time window w[0..4] of a point at window position WP.
 template <typename TA, int WP>
@@ -103,50 +152,89 @@ __device__ __forceinline__ void t_sums(const TA* w, TA& s1, TA& s2) {
        CW2<TA, WP, 4>() * w[4];
 }
 // Scatter of a time row's projected difference residuals (already weighted
-// by wC1, wC2) into the partial results of the planes of its window.
+// by wC1^2, wC2^2) into the partial results of the planes of its window:
+// one FMA per non-zero weight.
+template <typename TA, int WP, int K>
+__device__ __forceinline__ void t_push1(TA& a, TA q1, TA q2) {
+  constexpr TA w1 = (TA)lag_d1(WP, K), w2 = (TA)lag_d2(WP, K);
+  if (w1 != (TA)0) a = fm(-w1, q1, a);
+  if (w2 != (TA)0) a = fm(-w2, q2, a);
+}
 template <typename TA, int WP>
 __device__ __forceinline__ void t_push(TA* acc, TA q1, TA q2) {
-  acc[4 - WP] -= CW1<TA, WP, 0>() * q1 + CW2<TA, WP, 0>() * q2;
-  acc[5 - WP] -= CW1<TA, WP, 1>() * q1 + CW2<TA, WP, 1>() * q2;
-  acc[6 - WP] -= CW1<TA, WP, 2>() * q1 + CW2<TA, WP, 2>() * q2;
-  acc[7 - WP] -= CW1<TA, WP, 3>() * q1 + CW2<TA, WP, 3>() * q2;
-  acc[8 - WP] -= CW1<TA, WP, 4>() * q1 + CW2<TA, WP, 4>() * q2;
+  t_push1<TA, WP, 0>(acc[4 - WP], q1, q2);
+  t_push1<TA, WP, 1>(acc[5 - WP], q1, q2);
+  t_push1<TA, WP, 2>(acc[6 - WP], q1, q2);
+  t_push1<TA, WP, 3>(acc[7 - WP], q1, q2);
+  t_push1<TA, WP, 4>(acc[8 - WP], q1, q2);
 }
-// Rows of a periodic axis (x or y) at a point from the staged u plane: window
-// sums and Taylor residuals; `w0` is the LDS address of the window start (the
-// point itself is at w0 + 2 sd), `sd` the LDS stride along the axis.
+
+// Rows of one axis at a point, before weighting: the 5-point difference
+// sums s1 = k c1, s2 = k c2 of its window, its Taylor differences
+// dp = u_i - u_{i+1}, dm = u_i - u_{i-1} (0 for a missing one-sided row),
+// and the right sides of the axis' normal equations for its derivative
+// unknowns (x1, x2):
+//   b1 = wT^2 (dp - dm) - wC1^2 s1,   b2 = wT^2 (dp + dm) / 2 - wC2^2 s2.
 template <typename TA>
-__device__ __forceinline__ void xy_rows(const TA* su, int w0, int sd, TA ui, TA wT, TA wC1, TA wC2, TA& rTp,
-                                        TA& rTm, TA& rC1, TA& rC2) {
-  const TA w0v = su[w0], w1v = su[w0 + sd], w3v = su[w0 + 3 * sd], w4v = su[w0 + 4 * sd];
-  const TA s1 = CW1<TA, 2, 0>() * w0v + CW1<TA, 2, 1>() * w1v + CW1<TA, 2, 3>() * w3v + CW1<TA, 2, 4>() * w4v;
-  const TA s2 = CW2<TA, 2, 0>() * w0v + CW2<TA, 2, 1>() * w1v + CW2<TA, 2, 2>() * ui + CW2<TA, 2, 3>() * w3v +
-                CW2<TA, 2, 4>() * w4v;
-  rTp = wT * (ui - w3v);
-  rTm = wT * (ui - w1v);
-  rC1 = -wC1 * s1;
-  rC2 = -wC2 * s2;
+struct ARows {
+  TA c1, c2, dp, dm, b1, b2;
+};
+// Window centred on the point (position 2): the weights are
+// (1, -8, 0, 8, -1) / 12 and (-1, 16, -30, 16, -1) / 12, so c1 = 12 s1 and
+// c2 = 12 s2 are formed from shared sums and differences, and the factor
+// 1/12 is folded into B1d = wC1^2 / 12, B2d = wC2^2 / 12.
+template <typename TA>
+__device__ __forceinline__ ARows<TA> crows(TA wm2, TA wm1, TA ui, TA wp1, TA wp2, TA A, TA Ah, TA B1d, TA B2d) {
+  ARows<TA> r;
+  const TA d31 = wp1 - wm1, s13 = wm1 + wp1;
+  r.c1 = fm((TA)8, d31, wm2 - wp2);
+  r.c2 = fm((TA)-30, ui, fm((TA)16, s13, -(wm2 + wp2)));
+  r.dp = ui - wp1;
+  r.dm = ui - wm1;
+  r.b1 = -fm(A, d31, B1d * r.c1);                      // dp - dm = u_{i-1} - u_{i+1}
+  r.b2 = fm(Ah, fm((TA)2, ui, -s13), -(B2d * r.c2));   // dp + dm = 2 u_i - u_{i-1} - u_{i+1}
+  return r;
+}
+// Window at position WP on the (non-periodic) time axis: plain sums (k = 1).
+template <typename TA, int WP>
+__device__ __forceinline__ ARows<TA> wrows(const TA* w, TA A, TA Ah, TA B1, TA B2) {
+  ARows<TA> r;
+  t_sums<TA, WP>(w, r.c1, r.c2);
+  r.dp = WP != 4 ? w[WP] - w[WP != 4 ? WP + 1 : WP] : (TA)0;
+  r.dm = WP != 0 ? w[WP] - w[WP != 0 ? WP - 1 : WP] : (TA)0;
+  r.b1 = A * (r.dp - r.dm) - B1 * r.c1;
+  r.b2 = Ah * (r.dp + r.dm) - B2 * r.c2;
+  return r;
+}
+
+// Rows of a periodic axis (x or y) from the staged u plane; `w0` is the LDS
+// address of the window start (the point itself is at w0 + 2 sd), `sd` the
+// LDS stride along the axis.
+template <typename TA>
+__device__ __forceinline__ ARows<TA> xy_rows(const TA* su, int w0, int sd, TA ui, TA A, TA Ah, TA B1d, TA B2d) {
+  return crows<TA>(su[w0], su[w0 + sd], ui, su[w0 + 3 * sd], su[w0 + 4 * sd], A, Ah, B1d, B2d);
 }
 
 // Gather of the projected rows of a periodic axis staged in LDS into the
-// result at a tile point.  Each slot holds the four weighted row residuals
-// of one point, (C1, C2, T+, T-); `a` is the point's slot, `sd` the slot
-// stride along the axis.  Row j + o contains j at window slot 2 - o; T+ of
-// j - 1 and T- of j + 1 end at j.
-__device__ __forceinline__ float xy_gather(const float4* q, int a, int sd) {
-  const float4 m2 = q[a - 2 * sd], m1 = q[a - sd], z = q[a], p1 = q[a + sd], p2 = q[a + 2 * sd];
-  float y = z.z + z.w - m1.z - p1.w;
-  y -= CW1<float, 2, 4>() * m2.x + CW2<float, 2, 4>() * m2.y;
-  y -= CW1<float, 2, 3>() * m1.x + CW2<float, 2, 3>() * m1.y;
-  y -= CW2<float, 2, 2>() * z.y;
-  y -= CW1<float, 2, 1>() * p1.x + CW2<float, 2, 1>() * p1.y;
-  y -= CW1<float, 2, 0>() * p2.x + CW2<float, 2, 0>() * p2.y;
-  return y;
+// result at a tile point.  Each slot holds the four projected row residuals
+// of one point before weighting, (C1, C2, T+, T-); the gather weights them
+// by A = wT^2 (Taylor rows) and wC1^2, wC2^2 (difference rows, passed as
+// B1d = wC1^2 / 12, B2d = wC2^2 / 12 against the 12-scaled centred
+// weights).  `a` is the point's slot, `sd` the slot stride along the axis.
+// Row j + o contains j at window slot 2 - o; T+ of j - 1 and T- of j + 1 end
+// at j.
+template <typename TA, typename S>
+__device__ __forceinline__ TA xy_gather(const S* q, int a, int sd, TA A, TA B1d, TA B2d) {
+  const S m2 = q[a - 2 * sd], m1 = q[a - sd], z = q[a], p1 = q[a + sd], p2 = q[a + 2 * sd];
+  const TA t = (z.z + z.w) - (m1.z + p1.w);
+  const TA c1 = fm((TA)8, m1.x - p1.x, p2.x - m2.x);                          // window slots 4, 3, 1, 0
+  const TA c2 = fm((TA)-30, z.y, fm((TA)16, m1.y + p1.y, -(m2.y + p2.y)));
+  return fm(A, t, -fm(B1d, c1, B2d * c2));
 }
 
-template <typename TA>
+template <int NTH>
 __device__ __forceinline__ double fblock_sum(double v) {
-  __shared__ double part[kFThreads / 64];
+  __shared__ double part[NTH / 64];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -155,24 +243,27 @@ __device__ __forceinline__ double fblock_sum(double v) {
   double s = 0;
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int w = 0; w < kFThreads / 64; ++w) s += part[w];
+    for (int w = 0; w < NTH / 64; ++w) s += part[w];
   }
   return s;
 }
 
 template <typename TA, typename TV, typename TC, int MODE, int NT>
-__global__ void __launch_bounds__(kFThreads) k_apply3(const FTile* __restrict__ tiles, FGeom g,
+__global__ void __launch_bounds__(fthreads<TA>()) k_apply3(const FTile* __restrict__ tiles, FGeom g,
                                                       const LInst* __restrict__ li, CIdx ci,
                                                       const TV* __restrict__ u, const TC* __restrict__ c,
                                                       TV* __restrict__ out, const TV* __restrict__ bvec,
                                                       TV* __restrict__ xv, TV* __restrict__ rv,
                                                       TV* __restrict__ dv, const TV* __restrict__ dinv,
                                                       int cheb_step, double* __restrict__ partial) {
-  static_assert(std::is_same<TV, float>::value && std::is_same<TC, float>::value, "FP32 data");
+  static_assert(std::is_same<TC, float>::value && std::is_same<TA, TV>::value, "FP32 coefficients, TA vectors");
   constexpr int NQ = kFMaxQ;
+  constexpr int NTH = fthreads<TA>();
+  constexpr unsigned VB = sizeof(TV);   // bytes of a vector element
+  using S4 = typename FSlot<TA>::type;
   extern __shared__ __align__(16) unsigned char fsm[];
   TA* su = reinterpret_cast<TA*>(fsm);     // [kFRing][uplane] staged u planes, plane p in slot p % kFRing
-  float4* sq = reinterpret_cast<float4*>(su + kFRing * g.uplane);   // [2][2][qplane] projected x, y rows
+  S4* sq = reinterpret_cast<S4*>(su + kFRing * g.uplane);   // [2][2][qplane] projected x, y rows
   const FTile tl = tiles[blockIdx.x];
   const LInst& L = li[tl.inst];
   // NT > 0: every instance of the launch has NT time planes (a compile-time
@@ -186,14 +277,14 @@ __global__ void __launch_bounds__(kFThreads) k_apply3(const FTile* __restrict__ 
   const int npts = X.qn * Y.qn;
 
   // ---- the row points owned by this thread (the same (x, y) on every plane):
-  // q-point tid + s * kFThreads, s < NQ
+  // q-point tid + s * NTH, s < NQ
   bool act[NQ], tile[NQ];
   int ad[NQ], axw[NQ], ayw[NQ], qsl[NQ], qdx[NQ], qdy[NQ];
-  unsigned go[NQ];   // byte offset of the point within a plane (0 if none)
-  unsigned gt[NQ];   // the same for tile points, kOOB for halo points
+  unsigned go[NQ];   // byte offset of the point's coefficient within a plane (0 if none)
+  unsigned gt[NQ];   // byte offset of its vector element for tile points, kOOB for halo points
 #pragma unroll
   for (int s = 0; s < NQ; ++s) {
-    const int qi = tid + s * kFThreads;
+    const int qi = tid + s * NTH;
     act[s] = qi < npts;
     const int lx = act[s] ? qi / Y.qn : 0, ly = act[s] ? qi - lx * Y.qn : 0;
     const int gx = fwrap(X.qlo + lx, nx), gy = fwrap(Y.qlo + ly, ny);
@@ -214,16 +305,18 @@ __global__ void __launch_bounds__(kFThreads) k_apply3(const FTile* __restrict__ 
       else if (ly >= ny - 2) qdy[s] = qsl[s] - ny;
     }
     tile[s] = act[s] && (unsigned)(lx - X.ilo) < (unsigned)X.icnt && (unsigned)(ly - Y.ilo) < (unsigned)Y.icnt;
-    gt[s] = tile[s] ? go[s] : kOOB;
+    gt[s] = tile[s] ? go[s] * (VB / 4) : kOOB;
   }
 
   // Loads are raw buffer loads: a per-thread byte offset fixed over the
   // planes and a uniform plane offset.  Slots without a row point load point
   // 0 and planes past the end load the last plane; both are ignored.
-  const unsigned pbytes = 4u * (unsigned)stt;                 // one plane
-  const brsrc rU = mkbuf(u + L.voff, 4LL * L.N);
+  const unsigned pbytes = 4u * (unsigned)stt;                 // one coefficient plane
+  const unsigned vpbytes = VB * (unsigned)stt;                // one plane of a vector
+  const brsrc rU = mkbuf(u + L.voff, (long long)VB * L.N);
   const brsrc rC = mkbuf(c + L.coff, 4LL * L.N * ci.K);
   auto psoff = [&](int pl) { return (unsigned)(pl < nt ? pl : nt - 1) * pbytes; };
+  auto pvoff = [&](int pl) { return (unsigned)(pl < nt ? pl : nt - 1) * vpbytes; };
   // coefficient plane offsets (bytes) of c_phi and of the first / second
   // derivative of each axis; a missing field loads plane 0 and is zeroed by
   // its scale factor below
@@ -250,12 +343,12 @@ __global__ void __launch_bounds__(kFThreads) k_apply3(const FTile* __restrict__ 
   int uslot[kFMaxU];
 #pragma unroll
   for (int k = 0; k < kFMaxU; ++k) {
-    const int i = tid + k * kFThreads;
+    const int i = tid + k * NTH;
     uof[k] = 0;
     uslot[k] = g.uplane - 1;
     if (i < nus) {
       const int ux = i / Y.un, uy = i - ux * Y.un;
-      uof[k] = 4u * (unsigned)(fwrap(X.ulo + ux, nx) * stx + fwrap(Y.ulo + uy, ny) * sty);
+      uof[k] = VB * (unsigned)(fwrap(X.ulo + ux, nx) * stx + fwrap(Y.ulo + uy, ny) * sty);
       uslot[k] = i;
     }
   }
@@ -265,24 +358,25 @@ __global__ void __launch_bounds__(kFThreads) k_apply3(const FTile* __restrict__ 
   // fixed register name (a register copy would wait for the load):
   //   cs[q]  coefficients of the next plane of parity q to be processed,
   //   us[q]  u of the next plane of parity q to be staged in LDS.
-  TA cs[2][NQ][7], us[2][kFMaxU];
-  auto ld_coef = [&](int pl, TA(&d)[NQ][7]) {
+  TC cs[2][NQ][7];
+  TV us[2][kFMaxU];
+  auto ld_coef = [&](int pl, TC(&d)[NQ][7]) {
     const unsigned po = psoff(pl);
 #pragma unroll
     for (int s = 0; s < NQ; ++s)
 #pragma unroll
-      for (int k = 0; k < 7; ++k) d[s][k] = bld(rC, go[s], cko[k] + po);
+      for (int k = 0; k < 7; ++k) d[s][k] = bld<TC>(rC, go[s], cko[k] + po);
   };
-  auto ld_u = [&](int pl, TA(&d)[kFMaxU]) {
-    const unsigned po = psoff(pl);
+  auto ld_u = [&](int pl, TV(&d)[kFMaxU]) {
+    const unsigned po = pvoff(pl);
 #pragma unroll
-    for (int k = 0; k < kFMaxU; ++k) d[k] = bld(rU, uof[k], po);
+    for (int k = 0; k < kFMaxU; ++k) d[k] = bld<TV>(rU, uof[k], po);
   };
   // planes 0..4 staged before the loop; plane p + 5 is staged at plane p
   for (int pl = 0; pl < 5; ++pl) {
-    const unsigned po = psoff(pl);
+    const unsigned po = pvoff(pl);
 #pragma unroll
-    for (int k = 0; k < kFMaxU; ++k) su[slot(pl) + uslot[k]] = bld(rU, uof[k], po);
+    for (int k = 0; k < kFMaxU; ++k) su[slot(pl) + uslot[k]] = bld<TV>(rU, uof[k], po);
   }
   ld_coef(0, cs[0]);
   ld_coef(1, cs[1]);
@@ -290,15 +384,21 @@ __global__ void __launch_bounds__(kFThreads) k_apply3(const FTile* __restrict__ 
   ld_u(6, us[1]);
   __syncthreads();
 
-  const TA wT0 = (TA)L.wT[0], wC10 = (TA)L.wC1[0], wC20 = (TA)L.wC2[0];
-  const TA wTx = (TA)L.wT[1], wC1x = (TA)L.wC1[1], wC2x = (TA)L.wC2[1];
-  const TA wTy = (TA)L.wT[2], wC1y = (TA)L.wC1[2], wC2y = (TA)L.wC2[2];
+  // Per-axis constants (uniform; FP32 copies made by the host): squared row
+  // weights, coefficient scales (0 for a field the equation lacks) and the
+  // diagonal Gram inverses of two-sided rows (x and y are periodic, so all of
+  // their rows are two-sided).
+  auto kt = [&](int i) { return fkc<TA>(L, 0, i); };
+  auto kx = [&](int i) { return fkc<TA>(L, 1, i); };
+  auto ky = [&](int i) { return fkc<TA>(L, 2, i); };
+  const TA At = kt(FK_A), Aht = kt(FK_AH), B1t = kt(FK_B1), B2t = kt(FK_B2), B1dt = kt(FK_B1D), B2dt = kt(FK_B2D);
+  const TA Ax = kx(FK_A), Ahx = kx(FK_AH), B1dx = kx(FK_B1D), B2dx = kx(FK_B2D);
+  const TA Ay = ky(FK_A), Ahy = ky(FK_AH), B1dy = ky(FK_B1D), B2dy = ky(FK_B2D);
   auto has = [&](int k) { return ci.k[k] >= 0 ? (TA)1 : (TA)0; };
   const TA m0 = has(0);
-  const TA s1t = (TA)L.is1[0] * has(1), s2t = (TA)L.is2[0] * has(2), s1x = (TA)L.is1[1] * has(3);
-  const TA s2x = (TA)L.is2[1] * has(4), s1y = (TA)L.is1[2] * has(5), s2y = (TA)L.is2[2] * has(6);
-  const TA gx11 = (TA)L.gi[1][0][0], gx12 = (TA)L.gi[1][0][1], gx22 = (TA)L.gi[1][0][2];
-  const TA gy11 = (TA)L.gi[2][0][0], gy12 = (TA)L.gi[2][0][1], gy22 = (TA)L.gi[2][0][2];
+  const TA s1t = kt(FK_S1) * has(1), s2t = kt(FK_S2) * has(2), s1x = kx(FK_S1) * has(3);
+  const TA s2x = kx(FK_S2) * has(4), s1y = ky(FK_S1) * has(5), s2y = ky(FK_S2) * has(6);
+  const TA gx1 = kx(FK_G0), gx2 = kx(FK_G0 + 1), gy1 = ky(FK_G0), gy2 = ky(FK_G0 + 1);
 
   // Chebyshev coefficients of this step (uniform)
   TA chA = 0, chB = 0;
@@ -314,27 +414,27 @@ __global__ void __launch_bounds__(kFThreads) k_apply3(const FTile* __restrict__ 
 
   // Epilogue inputs of plane j (x, r, dinv for a Chebyshev step; b, dinv for
   // a residual), loaded one plane before the epilogue runs.
-  const long long vb = 4LL * L.N;
+  const long long vb = (long long)VB * L.N;
   const brsrc rOut = mkbuf(out ? out + L.voff : nullptr, out ? vb : 0);
   const brsrc rB = mkbuf(bvec ? bvec + L.voff : nullptr, bvec ? vb : 0);
   const brsrc rX = mkbuf(xv ? xv + L.voff : nullptr, xv ? vb : 0);
   const brsrc rR = mkbuf(rv ? rv + L.voff : nullptr, rv ? vb : 0);
   const brsrc rD = mkbuf(dv ? dv + L.voff : nullptr, dv ? vb : 0);
-  const brsrc rDi = mkbuf(dinv + L.voff, vb);
-  auto ld_epi = [&](int j, unsigned o, TA(&e)[3]) {
-    const unsigned pj = (unsigned)j * pbytes;
+  const brsrc rDi = mkbuf(dinv ? dinv + L.voff : nullptr, dinv ? vb : 0);
+  auto ld_epi = [&](int j, unsigned o, TV(&e)[3]) {
+    const unsigned pj = (unsigned)j * vpbytes;
     e[0] = e[1] = e[2] = 0;
     if (MODE == G_RESID) {
-      if (bvec) e[0] = bld(rB, o, pj);
-      if (dv) e[2] = bld(rDi, o, pj);
+      if (bvec) e[0] = bld<TV>(rB, o, pj);
+      if (dv) e[2] = bld<TV>(rDi, o, pj);
     } else if (MODE == G_CHEB) {
-      e[0] = bld(rX, o, pj);
-      e[1] = bld(rR, o, pj);
-      e[2] = bld(rDi, o, pj);
+      e[0] = bld<TV>(rX, o, pj);
+      e[1] = bld<TV>(rR, o, pj);
+      e[2] = bld<TV>(rDi, o, pj);
     }
   };
-  auto finalize = [&](int j, unsigned o, TA y, TA uj, const TA(&e)[3]) {
-    const unsigned pj = (unsigned)j * pbytes;
+  auto finalize = [&](int j, unsigned o, TA y, TA uj, const TV(&e)[3]) {
+    const unsigned pj = (unsigned)j * vpbytes;
     if (MODE == G_STORE) {
       bst(rOut, o, pj, y);
     } else if (MODE == G_STORE_DOT) {
@@ -351,7 +451,7 @@ __global__ void __launch_bounds__(kFThreads) k_apply3(const FTile* __restrict__ 
       bst(rD, o, pj, chA * uj + chB * e[2] * r);
     }
   };
-  TA es[2][NQ][3];                   // epilogue inputs by plane parity
+  TV es[2][NQ][3];                   // epilogue inputs by plane parity
 
   // One plane.  Phase A evaluates the rows at plane p (staged u slot p & 1)
   // and stores the projected x and y rows in row buffer p & 1, then stages
@@ -370,89 +470,85 @@ __global__ void __launch_bounds__(kFThreads) k_apply3(const FTile* __restrict__ 
     TA* nu = su + slot(p + 5);
     const int tw0 = slot(p - WP), tw1 = slot(p - WP + 1), tw2 = slot(p - WP + 2), tw3 = slot(p - WP + 3),
               tw4 = slot(p - WP + 4);
-    float4* qx = sq + Q * 2 * g.qplane;
-    float4* qy = qx + g.qplane;
-    const TA gt11 = (TA)L.gi[0][clt][0], gt12 = (TA)L.gi[0][clt][1], gt22 = (TA)L.gi[0][clt][2];
+    S4* qx = sq + Q * 2 * g.qplane;
+    S4* qy = qx + g.qplane;
+    // Gram inverse of this plane's time rows (one-sided on the first and
+    // last plane)
+    TA gt11, gt12 = 0, gt22;
+    if (clt == 0) {
+      gt11 = kt(FK_G0);
+      gt22 = kt(FK_G0 + 1);
+    } else {
+      constexpr int gk = clt == 1 ? FK_G1 : FK_G2;
+      gt11 = kt(gk);
+      gt12 = kt(gk + 1);
+      gt22 = kt(gk + 2);
+    }
     const bool onB = (L.dlo[0] && p == 0) || (L.dhi[0] && p == nt - 1);
 
 #pragma unroll
     for (int s = 0; s < NQ; ++s) {
       if (!act[s]) continue;
       TA* const ra = acc[s] + Q;
-      const TA* cc = cs[Q][s];
+      const TC* cc = cs[Q][s];
       // time window of the point (planes p - WP .. p - WP + 4)
       const TA w[5] = {su[tw0 + ad[s]], su[tw1 + ad[s]], su[tw2 + ad[s]], su[tw3 + ad[s]], su[tw4 + ad[s]]};
       const TA ui = w[WP];
-      // time rows
-      TA a1, a2;
-      t_sums<TA, WP>(w, a1, a2);
-      const TA rTpt = tpt ? wT0 * (ui - w[tpt ? WP + 1 : WP]) : (TA)0;
-      const TA rTmt = tmt ? wT0 * (ui - w[tmt ? WP - 1 : WP]) : (TA)0;
-      const TA rC1t = -wC10 * a1, rC2t = -wC20 * a2;
-      // x and y rows
-      TA rTpx, rTmx, rC1x, rC2x, rTpy, rTmy, rC1y, rC2y;
-      xy_rows<TA>(cu, axw[s], Y.un, ui, wTx, wC1x, wC2x, rTpx, rTmx, rC1x, rC2x);
-      xy_rows<TA>(cu, ayw[s], 1, ui, wTy, wC1y, wC2y, rTpy, rTmy, rC1y, rC2y);
-      // Sherman-Morrison scalar gamma
-      const TA c0 = cc[0] * m0;
-      const TA cat = cc[1] * s1t, catt = cc[2] * s2t;
-      const TA cax = cc[3] * s1x, caxx = cc[4] * s2x;
-      const TA cay = cc[5] * s1y, cayy = cc[6] * s2y;
-      const TA b1t = wT0 * (rTpt - rTmt) + wC10 * rC1t, b2t = wT0 * (rTpt + rTmt) * (TA)0.5 + wC20 * rC2t;
-      const TA b1x = wTx * (rTpx - rTmx) + wC1x * rC1x, b2x = wTx * (rTpx + rTmx) * (TA)0.5 + wC2x * rC2x;
-      const TA b1y = wTy * (rTpy - rTmy) + wC1y * rC1y, b2y = wTy * (rTpy + rTmy) * (TA)0.5 + wC2y * rC2y;
-      TA num = c0 * ui;
-      TA kap = 1;
-      {
-        const TA g1 = gt11 * b1t + gt12 * b2t, g2 = gt12 * b1t + gt22 * b2t;
-        const TA h1 = gt11 * cat + gt12 * catt, h2 = gt12 * cat + gt22 * catt;
-        kap += cat * h1 + catt * h2;
-        num -= cat * g1 + catt * g2;
+      // rows of the three axes (Eqs. 5-7) before weighting
+      const ARows<TA> rt = WP == 2 ? crows<TA>(w[0], w[1], ui, w[3], w[4], At, Aht, B1dt, B2dt)
+                                   : wrows<TA, WP>(w, At, Aht, B1t, B2t);
+      const ARows<TA> rx = xy_rows<TA>(cu, axw[s], Y.un, ui, Ax, Ahx, B1dx, B2dx);
+      const ARows<TA> ry = xy_rows<TA>(cu, ayw[s], 1, ui, Ay, Ahy, B1dy, B2dy);
+      constexpr TA kt_ = WP == 2 ? (TA)1 / (TA)12 : (TA)1;   // s = k c on the time axis
+      constexpr TA kc_ = (TA)1 / (TA)12;                      // x and y windows are centred
+      // scaled coefficients of the derivative unknowns in the equation row
+      const TA c0 = (TA)cc[0] * m0;
+      const TA cat = (TA)cc[1] * s1t, catt = (TA)cc[2] * s2t;
+      const TA cax = (TA)cc[3] * s1x, caxx = (TA)cc[4] * s2x;
+      const TA cay = (TA)cc[5] * s1y, cayy = (TA)cc[6] * s2y;
+      const TA b1t = rt.b1, b2t = rt.b2, b1x = rx.b1, b2x = rx.b2, b1y = ry.b1, b2y = ry.b2;
+      // G^-1 b and G^-1 (c_a, c_aa) of each axis
+      TA g1t, g2t, h1t, h2t;
+      if (clt == 0) {
+        g1t = gt11 * b1t;
+        g2t = gt22 * b2t;
+        h1t = gt11 * cat;
+        h2t = gt22 * catt;
+      } else {
+        g1t = gt11 * b1t + gt12 * b2t;
+        g2t = gt12 * b1t + gt22 * b2t;
+        h1t = gt11 * cat + gt12 * catt;
+        h2t = gt12 * cat + gt22 * catt;
       }
+      const TA g1x = gx1 * b1x, g2x = gx2 * b2x, h1x = gx1 * cax, h2x = gx2 * caxx;
+      const TA g1y = gy1 * b1y, g2y = gy2 * b2y, h1y = gy1 * cay, h2y = gy2 * cayy;
+      // Sherman-Morrison scalar gamma (kappa >= 1)
+      const TA kap = (TA)1 + cat * h1t + catt * h2t + cax * h1x + caxx * h2x + cay * h1y + cayy * h2y;
+      const TA num = c0 * ui - (cat * g1t + catt * g2t + cax * g1x + caxx * g2x + cay * g1y + cayy * g2y);
+      const TA gam = fdivk(num, kap);
+      // eliminated derivative unknowns x = -(G^-1 b + gamma G^-1 c), then the
+      // projected rows before weighting: C1 = x1 - s1, C2 = x2 - s2,
+      // T+ = dp + x1 + x2 / 2, T- = dm - x1 + x2 / 2
       {
-        const TA g1 = gx11 * b1x + gx12 * b2x, g2 = gx12 * b1x + gx22 * b2x;
-        const TA h1 = gx11 * cax + gx12 * caxx, h2 = gx12 * cax + gx22 * caxx;
-        kap += cax * h1 + caxx * h2;
-        num -= cax * g1 + caxx * g2;
-      }
-      {
-        const TA g1 = gy11 * b1y + gy12 * b2y, g2 = gy12 * b1y + gy22 * b2y;
-        const TA h1 = gy11 * cay + gy12 * cayy, h2 = gy12 * cay + gy22 * cayy;
-        kap += cay * h1 + cayy * h2;
-        num -= cay * g1 + cayy * g2;
-      }
-      const TA gam = num / kap;
-      // projected rows: the eliminated derivative unknowns x1, x2 of each
-      // axis, then the residuals of its rows, weighted for the gather
-      {
-        const TA e1 = b1x + cax * gam, e2 = b2x + caxx * gam;
-        const TA x1 = -(gx11 * e1 + gx12 * e2), x2 = -(gx12 * e1 + gx22 * e2);
-        const TA Q1 = wC1x * (rC1x + wC1x * x1), Q2 = wC2x * (rC2x + wC2x * x2);
-        const TA Tp = wTx * (rTpx + wTx * (x1 + (TA)0.5 * x2));
-        const TA Tm = wTx * (rTmx + wTx * (-x1 + (TA)0.5 * x2));
-        const int a = qsl[s];
-        const float4 v = make_float4(Q1, Q2, Tp, Tm);
-        qx[a] = v;
+        const TA x1 = -fm(h1x, gam, g1x), x2 = -fm(h2x, gam, g2x);
+        const S4 v = FSlot<TA>::make(fm(-kc_, rx.c1, x1), fm(-kc_, rx.c2, x2), fm((TA)0.5, x2, rx.dp) + x1,
+                                     fm((TA)0.5, x2, rx.dm) - x1);
+        qx[qsl[s]] = v;
         if (qdx[s] >= 0) qx[qdx[s]] = v;
       }
       {
-        const TA e1 = b1y + cay * gam, e2 = b2y + cayy * gam;
-        const TA x1 = -(gy11 * e1 + gy12 * e2), x2 = -(gy12 * e1 + gy22 * e2);
-        const TA Q1 = wC1y * (rC1y + wC1y * x1), Q2 = wC2y * (rC2y + wC2y * x2);
-        const TA Tp = wTy * (rTpy + wTy * (x1 + (TA)0.5 * x2));
-        const TA Tm = wTy * (rTmy + wTy * (-x1 + (TA)0.5 * x2));
-        const int a = qsl[s];
-        const float4 v = make_float4(Q1, Q2, Tp, Tm);
-        qy[a] = v;
+        const TA x1 = -fm(h1y, gam, g1y), x2 = -fm(h2y, gam, g2y);
+        const S4 v = FSlot<TA>::make(fm(-kc_, ry.c1, x1), fm(-kc_, ry.c2, x2), fm((TA)0.5, x2, ry.dp) + x1,
+                                     fm((TA)0.5, x2, ry.dm) - x1);
+        qy[qsl[s]] = v;
         if (qdy[s] >= 0) qy[qdy[s]] = v;
       }
       if (tile[s]) {
-        const TA e1 = b1t + cat * gam, e2 = b2t + catt * gam;
-        const TA x1 = -(gt11 * e1 + gt12 * e2), x2 = -(gt12 * e1 + gt22 * e2);
-        const TA Q1 = wC10 * (rC1t + wC10 * x1), Q2 = wC20 * (rC2t + wC20 * x2);
-        const TA Tp = tpt ? wT0 * (rTpt + wT0 * (x1 + (TA)0.5 * x2)) : (TA)0;
-        const TA Tm = tmt ? wT0 * (rTmt + wT0 * (-x1 + (TA)0.5 * x2)) : (TA)0;
-        TA e = c0 * gam + Tp + Tm;                     // equation row (q_E = gamma), own Taylor rows
+        const TA x1 = -fm(h1t, gam, g1t), x2 = -fm(h2t, gam, g2t);
+        const TA Q1 = B1t * fm(-kt_, rt.c1, x1), Q2 = B2t * fm(-kt_, rt.c2, x2);
+        const TA Tp = tpt ? At * (fm((TA)0.5, x2, rt.dp) + x1) : (TA)0;
+        const TA Tm = tmt ? At * (fm((TA)0.5, x2, rt.dm) - x1) : (TA)0;
+        TA e = fm(c0, gam, Tp + Tm);                 // equation row (q_E = gamma), own Taylor rows
         if (onB) e += ui;                              // boundary row
         ra[4] += e;
         ra[5] -= Tp;                                   // T+ of plane p ends at p + 1
@@ -480,7 +576,7 @@ __global__ void __launch_bounds__(kFThreads) k_apply3(const FTile* __restrict__ 
     for (int s = 0; s < NQ; ++s) {
       TA* const ra = acc[s] + Q;
       if (tile[s])
-        ra[4] += xy_gather(qx, qsl[s], Y.qs) + xy_gather(qy, qsl[s], 1);
+        ra[4] += xy_gather<TA>(qx, qsl[s], Y.qs, Ax, B1dx, B2dx) + xy_gather<TA>(qy, qsl[s], 1, Ay, B1dy, B2dy);
       // plane p - 2 is complete unless it is one of the last five planes
       // (those are written after the last plane)
       if (WP >= 2) finalize(p - 2, (p - 2 < nt - 5) ? gt[s] : kOOB, ra[2], su[slot(p - 2) + ad[s]], es[Q][s]);
@@ -489,7 +585,7 @@ __global__ void __launch_bounds__(kFThreads) k_apply3(const FTile* __restrict__ 
         for (int k = 0; k < 5; ++k) {
           const int j = p - 4 + k;
           if (j >= 0 && j >= nt - 5) {
-            TA e[3];
+            TV e[3];
             ld_epi(j, gt[s], e);
             finalize(j, gt[s], ra[k], su[slot(j) + ad[s]], e);
           }
@@ -527,7 +623,7 @@ __global__ void __launch_bounds__(kFThreads) k_apply3(const FTile* __restrict__ 
     step(p + 1, I1(), I4());
   }
   if (MODE == G_STORE_DOT) {
-    const double sdot = fblock_sum<TA>((double)dot);
+    const double sdot = fblock_sum<NTH>((double)dot);
     if (threadIdx.x == 0) partial[tl.pad] = sdot;
   }
 }
@@ -550,10 +646,10 @@ static void apply3_one(hipStream_t st, const FTile* tiles, int nb, FGeom g, cons
     granted[dev] = want;
   }
   if (e0 && e1)   // timed: the events take the dispatch's own start and end times
-    hipExtLaunchKernelGGL((k_apply3<TA, TV, TC, M, T>), dim3((unsigned)nb), dim3(kFThreads), lds, st, e0, e1, 0,
+    hipExtLaunchKernelGGL((k_apply3<TA, TV, TC, M, T>), dim3((unsigned)nb), dim3(fthreads<TA>()), lds, st, e0, e1, 0,
                           tiles, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial);
   else
-    hipLaunchKernelGGL((k_apply3<TA, TV, TC, M, T>), dim3((unsigned)nb), dim3(kFThreads), lds, st, tiles, g, li, ci,
+    hipLaunchKernelGGL((k_apply3<TA, TV, TC, M, T>), dim3((unsigned)nb), dim3(fthreads<TA>()), lds, st, tiles, g, li, ci,
                        u, c, out, bvec, x, r, d, dinv, cheb_step, partial);
 }
 
@@ -561,9 +657,12 @@ template <typename TA, typename TV, typename TC, int M>
 static void apply3_mode(hipStream_t st, const FTile* tiles, int nb, FGeom g, const LInst* li, CIdx ci, const TV* u,
                         const TC* c, TV* out, const TV* bvec, TV* x, TV* r, TV* d, const TV* dinv, int cheb_step,
                         double* partial, size_t lds, hipEvent_t e0, hipEvent_t e1) {
-  if (g.nt == 32)
-    apply3_one<TA, TV, TC, M, 32>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv,
-                                                         cheb_step, partial, lds, e0, e1);
+  // (the FP64 dot-product pass has no unrolled variant: it would not fit the
+  // register file)
+  constexpr bool unroll = !(sizeof(TA) == 8 && M == G_STORE_DOT);
+  if (unroll && g.nt == 32)
+    apply3_one<TA, TV, TC, M, unroll ? 32 : 0>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step,
+                                                partial, lds, e0, e1);
   else
     apply3_one<TA, TV, TC, M, 0>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial, lds,
                                  e0, e1);
@@ -574,7 +673,7 @@ void launch_apply3(hipStream_t st, const FTile* tiles, int nb, FGeom g, const LI
                    const TC* c, int mode, TV* out, const TV* bvec, TV* x, TV* r, TV* d, const TV* dinv,
                    int cheb_step, double* partial, hipEvent_t e0, hipEvent_t e1) {
   if (nb <= 0) return;
-  const size_t lds = sizeof(TA) * (kFRing * (size_t)g.uplane + 16 * (size_t)g.qplane);   // qplane: float4 slots x 4
+  const size_t lds = sizeof(TA) * (kFRing * (size_t)g.uplane + 16 * (size_t)g.qplane);   // qplane: 4-value slots x 4
   switch (mode) {
     case G_STORE:
       apply3_mode<TA, TV, TC, G_STORE>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial, lds, e0, e1);
@@ -595,5 +694,9 @@ void launch_apply3(hipStream_t st, const FTile* tiles, int nb, FGeom g, const LI
 template void launch_apply3<float, float, float>(hipStream_t, const FTile*, int, FGeom, const LInst*, CIdx,
                                                  const float*, const float*, int, float*, const float*, float*,
                                                  float*, float*, const float*, int, double*, hipEvent_t, hipEvent_t);
+template void launch_apply3<double, double, float>(hipStream_t, const FTile*, int, FGeom, const LInst*, CIdx,
+                                                   const double*, const float*, int, double*, const double*, double*,
+                                                   double*, double*, const double*, int, double*, hipEvent_t,
+                                                   hipEvent_t);
 
 }  // namespace mpde

@@ -5,7 +5,12 @@
 
 namespace mpde {
 
-constexpr int kFThreads = 768;   // threads per block
+constexpr int kFThreads = 768;   // threads per block, FP32 arithmetic
+constexpr int kFThreads64 = 512; // threads per block, FP64 arithmetic (twice the registers per value)
+template <typename TA>
+constexpr int fthreads() {
+  return sizeof(TA) == 8 ? kFThreads64 : kFThreads;
+}
 constexpr int kFMaxQ = 1;        // row points per thread and plane
 constexpr int kFRing = 10;       // staged u planes kept in LDS
 
@@ -70,7 +75,9 @@ __host__ __device__ inline FSpan fspan(int x0, int T, int n, int per) {
 
 // y = S u (no right-hand-side terms) with the epilogue of `mode`
 // (GatherMode); every instance of the tile table must have periodic x and y
-// axes and a non-periodic time axis of at least five points.  With events
+// axes and a non-periodic time axis of at least five points, and the table
+// must be cut for fthreads<TA>() threads.  Instantiated for FP32 (all modes)
+// and FP64 (vectors and arithmetic in FP64, coefficients FP32).  With events
 // e0, e1 the launch records the dispatch's start and end time in them.
 template <typename TA, typename TV, typename TC>
 void launch_apply3(hipStream_t st, const FTile* tiles, int nb, FGeom g, const LInst* li, CIdx ci, const TV* u,

@@ -55,6 +55,26 @@ struct LInst {
   long long voff;      // offset (points) of this instance in level vectors
   long long coff;      // offset (elements) of its coefficient block (K planes)
   long long doff;      // offset (elements) of its dense coarsest inverse
+  // FP32 copies of per-axis constants for the fused operator (FK_* indices):
+  // wT^2, wT^2 / 2, wC1^2, wC2^2, 1/s, 1/s^2, the Gram inverses and
+  // wC1^2 / 12, wC2^2 / 12.
+  float fk[kMaxD][16];
+};
+
+// Indices into LInst::fk.  Class 0 (both Taylor rows) has a diagonal Gram
+// block, so only its two diagonal entries are kept.
+enum FConst {
+  FK_A = 0,     // wT^2
+  FK_AH = 1,    // wT^2 / 2
+  FK_B1 = 2,    // wC1^2
+  FK_B2 = 3,    // wC2^2
+  FK_S1 = 4,    // 1 / s
+  FK_S2 = 5,    // 1 / s^2
+  FK_G0 = 6,    // class 0: i11, i22
+  FK_G1 = 8,    // class 1: i11, i12, i22
+  FK_G2 = 11,   // class 2: i11, i12, i22
+  FK_B1D = 14,  // wC1^2 / 12 (the centred 5-point weights are multiples of 1/12)
+  FK_B2D = 15,  // wC2^2 / 12
 };
 
 // Variable -> coefficient plane (-1 = no field).

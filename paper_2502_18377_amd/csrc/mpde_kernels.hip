@@ -730,50 +730,80 @@ __global__ void __launch_bounds__(kBlock) k_bb_factor(double* __restrict__ Lb, c
                                                       int* __restrict__ fail) {
   const long long base = boff[blockIdx.x];
   const int T = Tn[blockIdx.x], m = mn[blockIdx.x];
-  __shared__ double Dg[kBBMax][kBBMax + 1];
+  __shared__ double Ls[kBBMax][kBBMax + 1];            // Ls[k][r] = L[r][k], the factor's columns
+  __shared__ double col[2][kBBMax], xr[2][kBBMax];     // broadcast pivot column / inverse row
   __shared__ __align__(16) double S1[kBBMax * kBBT];   // staged A^T
   __shared__ __align__(16) double S2[kBBMax * kBBT];   // staged B^T
   const int tid = threadIdx.x;
   const int tr = tid >> 4, tc = tid & 15;
+  // diagonal-block factor and inverse: thread (r, cb) keeps columns
+  // c = cb + 4 i (i < 16) of row r in registers; a plane of m < 64 points
+  // is padded with an identity block
+  const int r = tid >> 2, cb = tid & 3;
   for (int j = 0; j < T; ++j) {
     double* Bjj = Lb + bb_at(base, j, 0, m);
-    for (int e = tid; e < m * m; e += blockDim.x) Dg[e / m][e % m] = Bjj[e];
-    __syncthreads();
-    // unblocked Cholesky of the diagonal block (lower)
-    for (int k = 0; k < m; ++k) {
-      if (tid == 0) {
-        const double a = Dg[k][k];
-        if (!(a > 0)) fail[blockIdx.x] = 1;
-        Dg[k][k] = a > 0 ? sqrt(a) : 1.0;
-      }
-      __syncthreads();
-      const double piv = Dg[k][k];
-      for (int r = k + 1 + tid; r < m; r += blockDim.x) Dg[r][k] /= piv;
-      __syncthreads();
-      for (int e = tid; e < (m - k - 1) * (m - k - 1); e += blockDim.x) {
-        const int r = k + 1 + e / (m - k - 1), cc = k + 1 + e % (m - k - 1);
-        if (cc <= r) Dg[r][cc] -= Dg[r][k] * Dg[cc][k];
-      }
-      __syncthreads();
+    double a[16], x[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int c = cb + 4 * i;
+      a[i] = (r < m && c < m) ? Bjj[r * m + c] : (r == c ? 1.0 : 0.0);
+      x[i] = (r == c) ? 1.0 : 0.0;
     }
-    // inverse of the lower-triangular factor, column c by forward
-    // substitution, written transposed into S2: S2[q][c] = Linv[c][q], the
-    // staged B^T of the products B_ij Linv^T below
-    for (int e = tid; e < kBBMax * kBBT; e += blockDim.x) S2[e] = 0.0;
-    __syncthreads();
-    for (int cc = tid; cc < m; cc += blockDim.x) {
-      for (int r = cc; r < m; ++r) {
-        double acc = (r == cc) ? 1.0 : 0.0;
-        for (int q = cc; q < r; ++q) acc -= Dg[r][q] * S2[cc * kBBT + q];
-        S2[cc * kBBT + r] = acc / Dg[r][r];
+    // right-looking Cholesky, one barrier per pivot: the owners of column k
+    // publish its current values, then every row r > k applies
+    // a[r][c] -= a[r][k] a[c][k] / a[k][k] (k < c <= r) and column k is
+    // scaled into Ls
+#pragma unroll
+    for (int k = 0; k < kBBMax; ++k) {
+      double* ck = col[k & 1];
+      if (cb == (k & 3)) ck[r] = a[k >> 2];
+      __syncthreads();
+      double akk = ck[k];
+      if (!(akk > 0)) {
+        if (tid == 0) fail[blockIdx.x] = 1;
+        akk = 1.0;
+      }
+      const double piv = sqrt(akk), rinv = 1.0 / akk;
+      const double ark = ck[r];
+      if (cb == (k & 3)) Ls[k][r] = r >= k ? (r == k ? piv : ark / piv) : 0.0;
+      if (r > k) {
+        const double f = ark * rinv;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int c = cb + 4 * i;
+          if (4 * i + 3 > k && c > k && c <= r) a[i] = fma(-f, ck[c], a[i]);
+        }
       }
     }
-    __syncthreads();
-    // S2 holds Linv transposed per column: S2[c][r] = Linv[r][c]; the block
-    // stores Linv row-major (k_bb_solve* read the inverse there)
-    for (int e = tid; e < m * m; e += blockDim.x) {
-      const int r = e / m, cc = e % m;
-      Bjj[e] = S2[cc * kBBT + r];
+    // inverse X = L^-1 (lower), right-looking: row k of X is final once
+    // divided by L[k][k]; rows r > k then subtract L[r][k] X[k][:]
+#pragma unroll
+    for (int k = 0; k < kBBMax; ++k) {
+      double* xk = xr[k & 1];
+      const double dk = 1.0 / Ls[k][k];
+      if (r == k) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          x[i] *= dk;
+          xk[cb + 4 * i] = x[i];
+        }
+      }
+      __syncthreads();
+      if (r > k) {
+        const double lrk = Ls[k][r];
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+          if (4 * i <= k + 3 && cb + 4 * i <= k) x[i] = fma(-lrk, xk[cb + 4 * i], x[i]);
+      }
+    }
+    // Linv row-major into the diagonal block (k_bb_solve* read the inverse
+    // there), and transposed into S2 (S2[c][r] = Linv[r][c]), the staged B^T
+    // of the products B_ij Linv^T below
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int c = cb + 4 * i;
+      if (r < m && c < m) Bjj[r * m + c] = x[i];
+      S2[c * kBBT + r] = x[i];
     }
     // B^T operand of L_ij = B_ij Linv^T is Linv^T[q][c] = Linv[c][q] = S2[q][c]: in place.
     __syncthreads();
@@ -1506,87 +1536,91 @@ __global__ void __launch_bounds__(kBlock) k_bb_solve64(const int* __restrict__ i
   const int tid = threadIdx.x, r = tid >> 2, h = tid & 3, c0 = h * CW;
   const TV* B = bvec + L.voff;
   TV* X = xvec + L.voff;
-  TV pre[4][CW];
-  auto load_fwd = [&](int t) {
+  // The five blocks of a plane (k = 0: the diagonal-block inverse, k = 1..4
+  // the sub-diagonal blocks) are loaded one plane ahead into register sets
+  // indexed by plane parity; each loop is unrolled by two so that the sets
+  // keep fixed registers.
+  TV pre[2][5][CW];
+  // (a thread's 16 entries of a block row are contiguous and 16-byte
+  // aligned: block offsets are multiples of 4 elements)
+  auto load_fwd = [&](int t, TV(&d)[5][CW]) {
 #pragma unroll
-    for (int k = 1; k <= 4; ++k) {
+    for (int k = 0; k <= 4; ++k) {
       if (t - k >= 0 && t < T) {
-        const TV* Lk = Lb + bb_at(base, t, k, M) + r * M + c0;
+        const uint4* Lk = reinterpret_cast<const uint4*>(Lb + bb_at(base, t, k, M) + r * M + c0);
 #pragma unroll
-        for (int q = 0; q < CW; ++q) pre[k - 1][q] = Lk[q];
+        for (int v = 0; v < CW * (int)sizeof(TV) / 16; ++v) {
+          const uint4 x = Lk[v];
+          __builtin_memcpy(&d[k][v * 16 / sizeof(TV)], &x, 16);
+        }
       }
     }
   };
-  load_fwd(0);
-  for (int t = 0; t < T; ++t) {
+  auto fwd = [&](int t, TV(&cur)[5][CW], TV(&nxt)[5][CW]) {
     double s = (h == 0) ? (double)B[(long long)t * M + r] : 0.0;
 #pragma unroll
     for (int k = 1; k <= 4; ++k)
       if (t - k >= 0) {
         const double* yk = ys + (t - k) * M + c0;
 #pragma unroll
-        for (int q = 0; q < CW; ++q) s -= (double)pre[k - 1][q] * yk[q];
+        for (int q = 0; q < CW; ++q) s -= (double)cur[k][q] * yk[q];
       }
-    TV dr[CW];
-    {
-      const TV* Di = Lb + bb_at(base, t, 0, M) + r * M + c0;
-#pragma unroll
-      for (int q = 0; q < CW; ++q) dr[q] = Di[q];
-    }
-    load_fwd(t + 1);
+    load_fwd(t + 1, nxt);
     s += __shfl_xor(s, 1, 64);
     s += __shfl_xor(s, 2, 64);
     if (h == 0) acc[r] = s;
     __syncthreads();
     double v = 0;
 #pragma unroll
-    for (int q = 0; q < CW; ++q) v += (double)dr[q] * acc[c0 + q];   // Dinv lower: upper entries are 0
+    for (int q = 0; q < CW; ++q) v += (double)cur[0][q] * acc[c0 + q];   // Dinv lower: upper entries are 0
     v += __shfl_xor(v, 1, 64);
     v += __shfl_xor(v, 2, 64);
     if (h == 0) ys[t * M + r] = v;
     __syncthreads();
+  };
+  load_fwd(0, pre[0]);
+  for (int t = 0; t < T; t += 2) {
+    fwd(t, pre[0], pre[1]);
+    if (t + 1 < T) fwd(t + 1, pre[1], pre[0]);
   }
   // backward: x_t = Dinv_t^T (y_t - sum_k L[t+k][k]^T x_{t+k}); thread (r, h)
   // accumulates column r over rows h*16..h*16+15 of each block.
-  auto load_bwd = [&](int t) {
+  auto load_bwd = [&](int t, TV(&d)[5][CW]) {
 #pragma unroll
-    for (int k = 1; k <= 4; ++k) {
+    for (int k = 0; k <= 4; ++k) {
       if (t >= 0 && t + k < T) {
         const TV* Lk = Lb + bb_at(base, t + k, k, M);
 #pragma unroll
-        for (int q = 0; q < CW; ++q) pre[k - 1][q] = Lk[(c0 + q) * M + r];
+        for (int q = 0; q < CW; ++q) d[k][q] = Lk[(c0 + q) * M + r];
       }
     }
   };
-  load_bwd(T - 1);
-  for (int t = T - 1; t >= 0; --t) {
+  auto bwd = [&](int t, TV(&cur)[5][CW], TV(&nxt)[5][CW]) {
     double s = (h == 0) ? ys[t * M + r] : 0.0;
 #pragma unroll
     for (int k = 1; k <= 4; ++k)
       if (t + k < T) {
         const double* xk = ys + (t + k) * M + c0;
 #pragma unroll
-        for (int q = 0; q < CW; ++q) s -= (double)pre[k - 1][q] * xk[q];
+        for (int q = 0; q < CW; ++q) s -= (double)cur[k][q] * xk[q];
       }
-    TV dc[CW];
-    {
-      const TV* Di = Lb + bb_at(base, t, 0, M);
-#pragma unroll
-      for (int q = 0; q < CW; ++q) dc[q] = Di[(c0 + q) * M + r];
-    }
-    load_bwd(t - 1);
+    load_bwd(t - 1, nxt);
     s += __shfl_xor(s, 1, 64);
     s += __shfl_xor(s, 2, 64);
     if (h == 0) acc[r] = s;
     __syncthreads();
     double v = 0;
 #pragma unroll
-    for (int q = 0; q < CW; ++q) v += (double)dc[q] * acc[c0 + q];
+    for (int q = 0; q < CW; ++q) v += (double)cur[0][q] * acc[c0 + q];
     v += __shfl_xor(v, 1, 64);
     v += __shfl_xor(v, 2, 64);
-    __syncthreads();
     if (h == 0) { ys[t * M + r] = v; X[(long long)t * M + r] = (TV)v; }
     __syncthreads();
+  };
+  load_bwd(T - 1, pre[0]);
+  for (int t = T - 1; t >= 0; t -= 2) {
+    bwd(t, pre[0], pre[1]);
+    if (t - 1 >= 0) bwd(t - 1, pre[1], pre[0]);
   }
 }
 

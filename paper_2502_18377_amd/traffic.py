@@ -13,7 +13,7 @@ WRITE_SIZE; both count KiB per dispatch):
 calibration: counter KiB per copied byte), then what bench.py does: one
 build + solve of the benchmark workload (64 instances of 32x64x64, FP32)
 and the timing loops of the finest-grid operator (30 back-to-back passes
-per mode after one warm-up pass).  `summarize` averages the counters over
+per mode after one warm-up pass; mode 4 is the FP64 residual pass).  `summarize` averages the counters over
 the timing-loop dispatches of each mode (the launches the benchmark's
 roofline times), scales them by the copy's bytes-per-counter ratio and
 records the hash of the kernel source, so that bench.py reports the
@@ -35,7 +35,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 256 << 20
 KERNELS = {"apply3": ("k_apply3", "mpde_fused.hip")}
-LOOP_MODES = (2, 1, 3)      # the modes bench.py times, in its order
+LOOP_MODES = (2, 1, 3, 4)   # the modes bench.py times, in its order (4: the FP64 residual)
 LOOP_REPS = 30
 
 
@@ -77,10 +77,13 @@ def _rows(d):
 
 
 def _mode(kernel_name):
-    """Operator mode of a k_apply3 instantiation (its fourth template argument), -1 otherwise."""
+    """Key of a k_apply3 instantiation: its operator mode (fourth template
+    argument) as in Problem.time_operator, i.e. "4" for the FP64 residual
+    pass (arithmetic type double); None for other kernels."""
     if "k_apply3<" not in kernel_name:
-        return -1
-    return int(kernel_name.split("k_apply3<")[1].split(">")[0].split(",")[3])
+        return None
+    args = [a.strip() for a in kernel_name.split("k_apply3<")[1].split(">")[0].split(",")]
+    return "4" if args[0] == "double" else args[3]
 
 
 def _per_dispatch(rows, match):
@@ -115,16 +118,16 @@ def summarize(d_fetch, d_write, out_path):
             disp = _per_dispatch(rows, kname)
             if not disp:
                 continue
-            gmax = max(g for _, g, _m in disp.values())
             ent = res["kernels"].setdefault(key, {"source_sha": source_sha(src), "modes": {}})
             for mode in sorted({m for _, _, m in disp.values()}):
                 # the timing loop: the last LOOP_REPS finest-grid dispatches of the mode
+                gmax = max(g for _, g, m in disp.values() if m == mode)
                 seq = [v for d, (v, g, m) in sorted(disp.items(), key=lambda kv: int(kv[0]))
                        if g == gmax and m == mode]
                 fin = seq[-LOOP_REPS:]
                 if not fin:
                     continue
-                e = ent["modes"].setdefault(str(mode), {"loop_dispatches": len(fin)})
+                e = ent["modes"].setdefault(mode, {"loop_dispatches": len(fin)})
                 e[f"{name}_KiB_per_dispatch"] = sum(fin) / len(fin)
                 e[f"{name}_bytes_per_dispatch"] = sum(fin) / len(fin) * 1024.0 * scale[name]
     for ent in res["kernels"].values():
@@ -139,41 +142,58 @@ def summarize(d_fetch, d_write, out_path):
 def trace(path):
     with open(path) as f:
         rows = list(csv.DictReader(f))
+
+    def name_of(r):
+        return r["Kernel_Name"].split("(")[0].replace("void ", "")
+
+    def grid(r):
+        # launches of one instantiation differ by level: grid size and LDS
+        # bytes per block together identify the level
+        return (int(r.get("Grid_Size", r.get("Grid_Size_X", 0)) or 0),
+                int(r.get("Group_Segment_Size", r.get("LDS_Block_Size", 0)) or 0))
+
+    def dur(r):
+        return (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+
     agg = {}
-    fin = {}
-    gmax = max((int(r.get("Grid_Size", r.get("Grid_Size_X", 0))) for r in rows if "k_apply3" in r["Kernel_Name"]), default=0)
+    gmax = {}   # finest grid of each k_apply3 instantiation: its largest launch
     for r in rows:
-        name = r["Kernel_Name"].split("(")[0].replace("void ", "")
-        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+        name = name_of(r)
         a = agg.setdefault(name, [0, 0.0])
         a[0] += 1
-        a[1] += d
-        if "k_apply3" in name and int(r.get("Grid_Size", r.get("Grid_Size_X", 0))) == gmax:
+        a[1] += dur(r)
+        if "k_apply3" in name:
+            gmax[name] = max(gmax.get(name, 0), grid(r))
+    fin, loops = {}, {}
+    for r in rows:
+        name = name_of(r)
+        if "k_apply3" in name and grid(r) == gmax[name]:
             b = fin.setdefault(name, [0, 0.0])
             b[0] += 1
-            b[1] += d
+            b[1] += dur(r)
+            loops.setdefault(name, []).append((int(r["Dispatch_Id"]), dur(r)))
     tot = sum(v[1] for v in agg.values())
     print(f"# total kernel time {tot / 1e3:.2f} ms")
     print("kernel | calls | total_ms | avg_us | pct")
     for k, (n, t) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
         print(f"{k} | {n} | {t / 1e3:.2f} | {t / n:.2f} | {100 * t / tot:.2f}")
-    loops = {}
-    for r in rows:
-        name = r["Kernel_Name"].split("(")[0].replace("void ", "")
-        if "k_apply3" in name and int(r.get("Grid_Size", r.get("Grid_Size_X", 0))) == gmax:
-            loops.setdefault(name, []).append((int(r["Dispatch_Id"]),
-                                               (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3))
-    print(f"# timing loops of bench.py (last {LOOP_REPS} finest-grid dispatches of each k_apply3 mode)")
+    print(f"# timing loops of bench.py (last {LOOP_REPS} finest-grid dispatches of each k_apply3 instantiation)")
     for k, v in sorted(loops.items()):
         d = [t for _, t in sorted(v)][-LOOP_REPS:]
         print(f"{k} | {len(d)} | {sum(d) / 1e3:.2f} | {sum(d) / len(d):.2f}")
-    print(f"# finest-grid dispatches of k_apply3 (grid size {gmax}), whole run")
-    n_all = sum(v[0] for v in fin.values())
-    t_all = sum(v[1] for v in fin.values())
+    print("# finest-grid dispatches of each k_apply3 instantiation, whole run")
     for k, (n, t) in sorted(fin.items()):
-        print(f"{k} | {n} | {t / 1e3:.2f} | {t / n:.2f}")
-    if n_all:
-        print(f"all modes | {n_all} | {t_all / 1e3:.2f} | {t_all / n_all:.2f}")
+        print(f"{k} | grid {gmax[k][0]} lds {gmax[k][1]} | {n} | {t / 1e3:.2f} | {t / n:.2f}")
+    print("# every (grid, lds) class of each k_apply3 instantiation, whole run")
+    cls = {}
+    for r in rows:
+        name = name_of(r)
+        if "k_apply3" in name:
+            c = cls.setdefault((name, grid(r)), [0, 0.0])
+            c[0] += 1
+            c[1] += dur(r)
+    for (k, gl), (n, t) in sorted(cls.items()):
+        print(f"{k} | grid {gl[0]} lds {gl[1]} | {n} | {t / 1e3:.2f} | {t / n:.2f}")
 
 
 if __name__ == "__main__":
