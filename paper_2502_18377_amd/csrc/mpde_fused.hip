@@ -232,6 +232,7 @@ __device__ __forceinline__ TA xy_gather(const S* q, int a, int sd, TA A, TA B1d,
   return fm(A, t, -fm(B1d, c1, B2d * c2));
 }
 
+// Block sum (result in thread 0) for blocks of at most NTH threads.
 template <int NTH>
 __device__ __forceinline__ double fblock_sum(double v) {
   __shared__ double part[NTH / 64];
@@ -243,7 +244,8 @@ __device__ __forceinline__ double fblock_sum(double v) {
   double s = 0;
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int w = 0; w < NTH / 64; ++w) s += part[w];
+    for (int w = 0; w < NTH / 64; ++w)
+      if (w < (int)(blockDim.x >> 6)) s += part[w];
   }
   return s;
 }
@@ -258,7 +260,8 @@ __global__ void __launch_bounds__(fthreads<TA>()) k_apply3(const FTile* __restri
                                                       int cheb_step, double* __restrict__ partial) {
   static_assert(std::is_same<TC, float>::value && std::is_same<TA, TV>::value, "FP32 coefficients, TA vectors");
   constexpr int NQ = kFMaxQ;
-  constexpr int NTH = fthreads<TA>();
+  constexpr int NTH = fthreads<TA>();   // largest block; a launch uses g.nthr <= NTH threads
+  const int nthr = g.nthr;
   constexpr unsigned VB = sizeof(TV);   // bytes of a vector element
   using S4 = typename FSlot<TA>::type;
   extern __shared__ __align__(16) unsigned char fsm[];
@@ -277,14 +280,14 @@ __global__ void __launch_bounds__(fthreads<TA>()) k_apply3(const FTile* __restri
   const int npts = X.qn * Y.qn;
 
   // ---- the row points owned by this thread (the same (x, y) on every plane):
-  // q-point tid + s * NTH, s < NQ
+  // q-point tid + s * nthr, s < NQ
   bool act[NQ], tile[NQ];
   int ad[NQ], axw[NQ], ayw[NQ], qsl[NQ], qdx[NQ], qdy[NQ];
   unsigned go[NQ];   // byte offset of the point's coefficient within a plane (0 if none)
   unsigned gt[NQ];   // byte offset of its vector element for tile points, kOOB for halo points
 #pragma unroll
   for (int s = 0; s < NQ; ++s) {
-    const int qi = tid + s * NTH;
+    const int qi = tid + s * nthr;
     act[s] = qi < npts;
     const int lx = act[s] ? qi / Y.qn : 0, ly = act[s] ? qi - lx * Y.qn : 0;
     const int gx = fwrap(X.qlo + lx, nx), gy = fwrap(Y.qlo + ly, ny);
@@ -343,7 +346,7 @@ __global__ void __launch_bounds__(fthreads<TA>()) k_apply3(const FTile* __restri
   int uslot[kFMaxU];
 #pragma unroll
   for (int k = 0; k < kFMaxU; ++k) {
-    const int i = tid + k * NTH;
+    const int i = tid + k * nthr;
     uof[k] = 0;
     uslot[k] = g.uplane - 1;
     if (i < nus) {
@@ -646,10 +649,10 @@ static void apply3_one(hipStream_t st, const FTile* tiles, int nb, FGeom g, cons
     granted[dev] = want;
   }
   if (e0 && e1)   // timed: the events take the dispatch's own start and end times
-    hipExtLaunchKernelGGL((k_apply3<TA, TV, TC, M, T>), dim3((unsigned)nb), dim3(fthreads<TA>()), lds, st, e0, e1, 0,
+    hipExtLaunchKernelGGL((k_apply3<TA, TV, TC, M, T>), dim3((unsigned)nb), dim3((unsigned)g.nthr), lds, st, e0, e1, 0,
                           tiles, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial);
   else
-    hipLaunchKernelGGL((k_apply3<TA, TV, TC, M, T>), dim3((unsigned)nb), dim3(fthreads<TA>()), lds, st, tiles, g, li, ci,
+    hipLaunchKernelGGL((k_apply3<TA, TV, TC, M, T>), dim3((unsigned)nb), dim3((unsigned)g.nthr), lds, st, tiles, g, li, ci,
                        u, c, out, bvec, x, r, d, dinv, cheb_step, partial);
 }
 

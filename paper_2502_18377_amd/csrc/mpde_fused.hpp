@@ -26,6 +26,8 @@ struct FGeom {
   int uplane;        // elements of one staged u plane
   int qplane;        // float4 slots of one staged row-value plane
   int nt;            // time planes of every instance of the launch, 0 if they differ
+  int nthr;          // threads per block: the tiles' row points rounded up to whole
+                     // wavefronts (at most fthreads<TA>(); staged u slots <= 2 nthr)
 };
 
 // Ranges of one axis for a tile [x0, x0 + T) of an axis with n points:
@@ -76,7 +78,7 @@ __host__ __device__ inline FSpan fspan(int x0, int T, int n, int per) {
 // y = S u (no right-hand-side terms) with the epilogue of `mode`
 // (GatherMode); every instance of the tile table must have periodic x and y
 // axes and a non-periodic time axis of at least five points, and the table
-// must be cut for fthreads<TA>() threads.  Instantiated for FP32 (all modes)
+// must be cut for at most fthreads<TA>() threads (g.nthr per block).  Instantiated for FP32 (all modes)
 // and FP64 (vectors and arithmetic in FP64, coefficients FP32).  With events
 // e0, e1 the launch records the dispatch's start and end time in them.
 template <typename TA, typename TV, typename TC>

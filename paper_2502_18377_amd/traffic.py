@@ -147,10 +147,7 @@ def trace(path):
         return r["Kernel_Name"].split("(")[0].replace("void ", "")
 
     def grid(r):
-        # launches of one instantiation differ by level: grid size and LDS
-        # bytes per block together identify the level
-        return (int(r.get("Grid_Size", r.get("Grid_Size_X", 0)) or 0),
-                int(r.get("Group_Segment_Size", r.get("LDS_Block_Size", 0)) or 0))
+        return int(r.get("Grid_Size", r.get("Grid_Size_X", 0)) or 0)
 
     def dur(r):
         return (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
@@ -183,17 +180,24 @@ def trace(path):
         print(f"{k} | {len(d)} | {sum(d) / 1e3:.2f} | {sum(d) / len(d):.2f}")
     print("# finest-grid dispatches of each k_apply3 instantiation, whole run")
     for k, (n, t) in sorted(fin.items()):
-        print(f"{k} | grid {gmax[k][0]} lds {gmax[k][1]} | {n} | {t / 1e3:.2f} | {t / n:.2f}")
-    print("# every (grid, lds) class of each k_apply3 instantiation, whole run")
-    cls = {}
-    for r in rows:
+        print(f"{k} | grid {gmax[k]} | {n} | {t / 1e3:.2f} | {t / n:.2f}")
+    # multigrid level of each operator launch, from the dispatch order:
+    # k_restrict moves one level down, k_prolong_add one level up (launches
+    # outside a V-cycle count as level 0)
+    print("# k_apply3 by multigrid level (from restrict/prolong order), whole run")
+    lev, per = 0, {}
+    for r in sorted(rows, key=lambda r: int(r["Dispatch_Id"])):
         name = name_of(r)
-        if "k_apply3" in name:
-            c = cls.setdefault((name, grid(r)), [0, 0.0])
+        if "k_restrict" in name:
+            lev += 1
+        elif "k_prolong_add" in name:
+            lev = max(0, lev - 1)
+        elif "k_apply3" in name:
+            c = per.setdefault((name, lev), [0, 0.0])
             c[0] += 1
             c[1] += dur(r)
-    for (k, gl), (n, t) in sorted(cls.items()):
-        print(f"{k} | grid {gl[0]} lds {gl[1]} | {n} | {t / 1e3:.2f} | {t / n:.2f}")
+    for (k, l), (n, t) in sorted(per.items()):
+        print(f"{k} | level {l} | {n} | {t / 1e3:.2f} | {t / n:.2f}")
 
 
 if __name__ == "__main__":
