@@ -227,9 +227,14 @@ int mpde_net_create(int32_t in_channels, uint64_t seed, mpde_net **out);
 /* One Adam step (learning rate lr) on residual samples drawn from problem p
  * at grid level `level` (>= 1): a random right-hand side per instance is
  * smoothed on the finer levels and restricted, exactly as in a V-cycle.
- * *loss and *loss_plain (host, may be NULL) receive the mean normalised
- * energy loss of the learned correction and of the plain V-cycle's on the
- * same samples (lower is better; the exact coarse solve attains the minimum).
+ * The loss of a coarse correction o is the energy on the next finer level
+ * f = level - 1 of its prolongation, (P o)^T S_f (P o) - 2 (P o)^T r_f, with
+ * r_f the pre-smoothed finer residual, both normalised by ||R r_f||; its
+ * minimiser is the Galerkin coarse correction (P^T S_f P)^-1 P^T r_f, which
+ * the rediscretised coarse operator only approximates.  *loss and
+ * *loss_plain (host, may be NULL) receive the mean loss of the learned
+ * correction and of the plain V-cycle's on the same samples (lower is
+ * better).
  * Errors: INVALID_ARG (bad level / mismatched channels), UNSUPPORTED (FP64
  * problem), HIP. */
 int mpde_net_train_step(mpde_net *net, mpde_problem *p, int32_t level, uint64_t seed, double lr, double *loss,

@@ -397,7 +397,7 @@ void make_ftab(FTab& f, const std::vector<LInst>& h, int B, const std::vector<in
   // some tile does not fit a block
   struct Cut {
     long long tiles = 0, waves = 0;
-    int uplane = 0, qplane = 0;
+    int uplane = 0, qplane = 0, nthr = 0;
   };
   auto cut = [&](int TX, int TY, Cut& c) {
     c = Cut{};
@@ -412,9 +412,12 @@ void make_ftab(FTab& f, const std::vector<LInst>& h, int B, const std::vector<in
           c.waves += (X.qn * Y.qn + 63) / 64;
           c.uplane = std::max(c.uplane, X.un * Y.un);
           c.qplane = std::max(c.qplane, X.qs * Y.qs);
+          // block size: every row point, and every staged u slot within two per thread
+          c.nthr = std::max(c.nthr, std::max(X.qn * Y.qn, (X.un * Y.un + 1) / 2));
         }
     }
     c.uplane = (c.uplane + 1 + 3) & ~3;   // spare slot for idle threads' staging writes; 16-byte rows
+    c.nthr = (c.nthr + 63) / 64 * 64;
     return esize * (kFRing * (size_t)c.uplane + 16 * (size_t)c.qplane) <= 160000;   // LDS per block
   };
   std::vector<std::pair<int, int>> cand;   // larger tiles first (preferred on ties)
@@ -442,6 +445,7 @@ void make_ftab(FTab& f, const std::vector<LInst>& h, int B, const std::vector<in
   f.g.TY = TY;
   f.g.uplane = ok[bi].second.uplane;
   f.g.qplane = ok[bi].second.qplane;
+  f.g.nthr = ok[bi].second.nthr;
   f.g.nt = -1;
   std::vector<std::vector<FTile>> per(B);
   int slot = 0;
@@ -580,14 +584,22 @@ struct Solver {
     }
   }
 
-  // One training step of net on problem level l; returns the mean energy
-  // loss of the learned correction and (loss_plain) of the plain V-cycle's.
+  // One training step of net on problem level l >= 1; returns the mean loss
+  // of the learned correction and (loss_plain) of the plain V-cycle's.  The
+  // loss is the energy on the next finer level f = l - 1 of the prolonged
+  // coarse correction, E(o) = (P o)^T S_f (P o) - 2 (P o)^T r_f for the
+  // pre-smoothed residual r_f (both scaled by 1 / ||R r_f||): its minimiser
+  // is the Galerkin coarse correction, so the network learns what the
+  // rediscretised coarse operator and the recursive V-cycle miss for the
+  // finer level's smooth error.
   double train_step(mpde_net* net, int l, unsigned seed, double lr, double* loss_plain) {
     net_setup(l);
     NetScratch& S = P->ns;
     Level& L = P->lv[l];
-    sample_residuals(l, seed);
-    // plain coarse correction v = V_l(r) into a scratch level vector
+    Level& F = P->lv[l - 1];
+    const Table& tf = F.smooth;             // finer-level points of the instances that reach level l
+    sample_residuals(l, seed);              // F.r = pre-smoothed finer residual, L.b = R F.r
+    // plain coarse correction v = V_l(b) into a scratch level vector
     TV* v = (TV*)S.dB;                      // FP32 scratch, >= L.npts entries
     const bool keep = use_net;
     use_net = false;
@@ -596,21 +608,31 @@ struct Solver {
     level_norms(l, V(L.b));
     int nb_inst = 0;
     for (int b = 0; b < P->B; ++b) nb_inst += L.h[b].N > 0;
-    // reference: energy loss of the plain correction
+    // finer-level energy of the unit-scaled coarse correction o (level l
+    // vector); with dOut, also the network's output gradient
+    auto fine_energy = [&](TV* o, double* loss, float* dOut) {
+      launch_fill<TV>(st, tf.d, tf.nb(), F.d, V(F.dd), (TV)0);
+      launch_prolong_add<TV>(D, st, tf.d, tf.nb(), F.d, L.d, o, V(F.dd));       // p = P o
+      apply(l - 1, tf, V(F.dd), V(F.x), G_STORE, nullptr);                       // S_f p
+      energy_grad_launch(st, tf.d, tf.nb(), F.d, (const float*)F.dd, (const float*)F.x, (const float*)F.r, S.inv,
+                         (const float*)F.dinv, 1.0f, nullptr, P->partial);
+      finish(tf, loss);
+      if (dOut) {
+        fine_resid_launch(st, tf.d, tf.nb(), F.d, (const float*)F.x, (const float*)F.r, S.inv, (float*)F.dd);
+        launch_restrict<TV>(D, st, L.all.d, L.all.nb(), F.d, L.d, V(F.dd), V(L.r));   // R (S_f p - rhat)
+        grad_out_launch(st, L.all.d, L.all.nb(), L.d, (const float*)L.r, (const float*)L.dinv, 1.0f / nb_inst,
+                        dOut);
+      }
+    };
+    // reference: the plain correction
     scale_vec_launch(st, L.all.d, L.all.nb(), L.d, (const float*)v, S.inv, (float*)L.dd);
-    apply(l, L.all, V(L.dd), V(L.r), G_STORE, nullptr);
-    energy_grad_launch(st, L.all.d, L.all.nb(), L.d, (const float*)L.dd, (const float*)L.r, (const float*)L.b,
-                       S.inv, (const float*)L.dinv, 1.0f, nullptr, P->partial);
-    finish(L.all, P->rzp);
+    fine_energy(V(L.dd), P->rzp, nullptr);
     // learned correction
     features_launch(st, L.all.d, L.all.nb(), L.d, P->K, (const float*)L.b, (const float*)v, (const float*)L.dinv,
                     S.inv, (const float*)L.coef, S.X0);
     net_forward(net);
     predict_launch(st, L.all.d, L.all.nb(), L.d, S.Y3, (const float*)v, (const float*)L.dinv, S.inv, (float*)L.dd);
-    apply(l, L.all, V(L.dd), V(L.r), G_STORE, nullptr);
-    energy_grad_launch(st, L.all.d, L.all.nb(), L.d, (const float*)L.dd, (const float*)L.r, (const float*)L.b,
-                       S.inv, (const float*)L.dinv, 1.0f / nb_inst, S.dA, P->partial);
-    finish(L.all, P->rz);
+    fine_energy(V(L.dd), P->rz, S.dA);
     std::vector<double> lossb(P->B), lossp(P->B);
     HIPCHK(hipMemcpyAsync(lossb.data(), P->rz, P->B * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(lossp.data(), P->rzp, P->B * sizeof(double), hipMemcpyDeviceToHost, st));

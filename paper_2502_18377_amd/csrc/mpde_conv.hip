@@ -336,6 +336,36 @@ __global__ void __launch_bounds__(256) k_energy_grad(const Work* __restrict__ wo
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// Residual of the prolonged correction on the finer level of a coarse-grid
+// correction, w = S p - rhat with rhat = r / ||b|| (b the coarse right side).
+__global__ void __launch_bounds__(256) k_fine_resid(const Work* __restrict__ work, const LInst* __restrict__ li,
+                                                    const float* __restrict__ Sp, const float* __restrict__ r,
+                                                    const double* __restrict__ inv_norm, float* __restrict__ w) {
+  const Work wk = work[blockIdx.x];
+  const LInst& L = li[wk.inst];
+  const int p = wk.start + threadIdx.x;
+  if (p >= L.N) return;
+  const long long g = L.voff + p;
+  w[g] = (float)((double)Sp[g] - (double)r[g] * inv_norm[wk.inst]);
+}
+
+// Output gradient of the network for the finer-level energy of a prolonged
+// coarse correction: d loss / d o = 2 P^T w, and restriction is
+// P^T / 2^k (k halved axes), so with Rw = R w on the coarse level,
+// d loss / d n = D^-1 2 * 2^k Rw * scale.
+__global__ void __launch_bounds__(256) k_grad_out(const Work* __restrict__ work, const LInst* __restrict__ li,
+                                                  const float* __restrict__ Rw, const float* __restrict__ dinv,
+                                                  float scale, float* __restrict__ dOut) {
+  const Work wk = work[blockIdx.x];
+  const LInst& L = li[wk.inst];
+  const int p = wk.start + threadIdx.x;
+  if (p >= L.N) return;
+  const long long g = L.voff + p;
+  float* d = dOut + g * 16;
+  d[0] = (float)(2.0 * (double)(1 << L.ncoarsened) * (double)Rw[g] * (double)dinv[g]) * scale;
+  for (int k = 1; k < 16; ++k) d[k] = 0.f;
+}
+
 // o = v / ||r|| (the plain correction alone, for the reference loss).
 __global__ void __launch_bounds__(256) k_scale_vec(const Work* __restrict__ work, const LInst* __restrict__ li,
                                                    const float* __restrict__ v, const double* __restrict__ inv_norm,
@@ -369,6 +399,16 @@ void energy_grad_launch(hipStream_t st, const Work* w, int nb, const LInst* li, 
   if (nb <= 0) return;
   hipLaunchKernelGGL(k_energy_grad, dim3(nb), dim3(256), 0, st, w, li, o, So, r, inv_norm, dinv, scale, dOut,
                      partial);
+}
+void fine_resid_launch(hipStream_t st, const Work* w, int nb, const LInst* li, const float* Sp, const float* r,
+                       const double* inv_norm, float* out) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(k_fine_resid, dim3(nb), dim3(256), 0, st, w, li, Sp, r, inv_norm, out);
+}
+void grad_out_launch(hipStream_t st, const Work* w, int nb, const LInst* li, const float* Rw, const float* dinv,
+                     float scale, float* dOut) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(k_grad_out, dim3(nb), dim3(256), 0, st, w, li, Rw, dinv, scale, dOut);
 }
 void scale_vec_launch(hipStream_t st, const Work* w, int nb, const LInst* li, const float* v, const double* inv_norm,
                       float* o) {

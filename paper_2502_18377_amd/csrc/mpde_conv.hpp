@@ -36,6 +36,13 @@ void predict_launch(hipStream_t st, const Work* w, int nb, const LInst* li, cons
 void energy_grad_launch(hipStream_t st, const Work* w, int nb, const LInst* li, const float* o, const float* So,
                         const float* r, const double* inv_norm, const float* dinv, float scale, float* dOut,
                         double* partial);
+// w = S p - r / ||b|| on the finer level of a coarse-grid correction.
+void fine_resid_launch(hipStream_t st, const Work* w, int nb, const LInst* li, const float* Sp, const float* r,
+                       const double* inv_norm, float* out);
+// Network output gradient D^-1 2 * 2^k (R w) * scale from the restricted
+// finer-level residual R w (k = halved axes of the coarse level).
+void grad_out_launch(hipStream_t st, const Work* w, int nb, const LInst* li, const float* Rw, const float* dinv,
+                     float scale, float* dOut);
 void scale_vec_launch(hipStream_t st, const Work* w, int nb, const LInst* li, const float* v, const double* inv_norm,
                       float* o);
 }  // namespace mpde
