@@ -250,14 +250,18 @@ __device__ __forceinline__ double fblock_sum(double v) {
   return s;
 }
 
-template <typename TA, typename TV, typename TC, int MODE, int NT>
+// SIG: y = A_u^T Pi (A_u u - d) with the right-hand-side terms of the
+// source `fsrc` (equation rows) and the boundary values `wsrc` (boundary
+// rows), both level-0 point fields.
+template <typename TA, typename TV, typename TC, int MODE, int NT, bool SIG>
 __global__ void __launch_bounds__(fthreads<TA>()) k_apply3(const FTile* __restrict__ tiles, FGeom g,
                                                       const LInst* __restrict__ li, CIdx ci,
                                                       const TV* __restrict__ u, const TC* __restrict__ c,
                                                       TV* __restrict__ out, const TV* __restrict__ bvec,
                                                       TV* __restrict__ xv, TV* __restrict__ rv,
                                                       TV* __restrict__ dv, const TV* __restrict__ dinv,
-                                                      int cheb_step, double* __restrict__ partial) {
+                                                      int cheb_step, double* __restrict__ partial,
+                                                      const TC* __restrict__ fsrc, const TC* __restrict__ wsrc) {
   static_assert(std::is_same<TC, float>::value && std::is_same<TA, TV>::value, "FP32 coefficients, TA vectors");
   constexpr int NQ = kFMaxQ;
   constexpr int NTH = fthreads<TA>();   // largest block; a launch uses g.nthr <= NTH threads
@@ -318,6 +322,9 @@ __global__ void __launch_bounds__(fthreads<TA>()) k_apply3(const FTile* __restri
   const unsigned vpbytes = VB * (unsigned)stt;                // one plane of a vector
   const brsrc rU = mkbuf(u + L.voff, (long long)VB * L.N);
   const brsrc rC = mkbuf(c + L.coff, 4LL * L.N * ci.K);
+  const brsrc rF = mkbuf(SIG ? fsrc + L.voff : nullptr, SIG ? 4LL * L.N : 0);
+  const brsrc rW = mkbuf(SIG ? wsrc + L.voff : nullptr, SIG ? 4LL * L.N : 0);
+  constexpr int NC = SIG ? 8 : 7;   // per-plane point loads: the coefficient planes (and the source)
   auto psoff = [&](int pl) { return (unsigned)(pl < nt ? pl : nt - 1) * pbytes; };
   auto pvoff = [&](int pl) { return (unsigned)(pl < nt ? pl : nt - 1) * vpbytes; };
   // coefficient plane offsets (bytes) of c_phi and of the first / second
@@ -361,14 +368,16 @@ __global__ void __launch_bounds__(fthreads<TA>()) k_apply3(const FTile* __restri
   // fixed register name (a register copy would wait for the load):
   //   cs[q]  coefficients of the next plane of parity q to be processed,
   //   us[q]  u of the next plane of parity q to be staged in LDS.
-  TC cs[2][NQ][7];
+  TC cs[2][NQ][NC];
   TV us[2][kFMaxU];
-  auto ld_coef = [&](int pl, TC(&d)[NQ][7]) {
+  auto ld_coef = [&](int pl, TC(&d)[NQ][NC]) {
     const unsigned po = psoff(pl);
 #pragma unroll
-    for (int s = 0; s < NQ; ++s)
+    for (int s = 0; s < NQ; ++s) {
 #pragma unroll
       for (int k = 0; k < 7; ++k) d[s][k] = bld<TC>(rC, go[s], cko[k] + po);
+      if (SIG) d[s][NC - 1] = bld<TC>(rF, go[s], po);
+    }
   };
   auto ld_u = [&](int pl, TV(&d)[kFMaxU]) {
     const unsigned po = pvoff(pl);
@@ -527,7 +536,8 @@ __global__ void __launch_bounds__(fthreads<TA>()) k_apply3(const FTile* __restri
       const TA g1y = gy1 * b1y, g2y = gy2 * b2y, h1y = gy1 * cay, h2y = gy2 * cayy;
       // Sherman-Morrison scalar gamma (kappa >= 1)
       const TA kap = (TA)1 + cat * h1t + catt * h2t + cax * h1x + caxx * h2x + cay * h1y + cayy * h2y;
-      const TA num = c0 * ui - (cat * g1t + catt * g2t + cax * g1x + caxx * g2x + cay * g1y + cayy * g2y);
+      const TA rhoE = SIG ? c0 * ui - (TA)cc[NC - 1] : c0 * ui;   // equation-row residual
+      const TA num = rhoE - (cat * g1t + catt * g2t + cax * g1x + caxx * g2x + cay * g1y + cayy * g2y);
       const TA gam = fdivk(num, kap);
       // eliminated derivative unknowns x = -(G^-1 b + gamma G^-1 c), then the
       // projected rows before weighting: C1 = x1 - s1, C2 = x2 - s2,
@@ -552,7 +562,7 @@ __global__ void __launch_bounds__(fthreads<TA>()) k_apply3(const FTile* __restri
         const TA Tp = tpt ? At * (fm((TA)0.5, x2, rt.dp) + x1) : (TA)0;
         const TA Tm = tmt ? At * (fm((TA)0.5, x2, rt.dm) - x1) : (TA)0;
         TA e = fm(c0, gam, Tp + Tm);                 // equation row (q_E = gamma), own Taylor rows
-        if (onB) e += ui;                              // boundary row
+        if (onB) e += SIG ? ui - (TA)bld<TC>(rW, go[s], psoff(p)) : ui;   // boundary row
         ra[4] += e;
         ra[5] -= Tp;                                   // T+ of plane p ends at p + 1
         ra[3] -= Tm;                                   // T- of plane p ends at p - 1
@@ -631,10 +641,10 @@ __global__ void __launch_bounds__(fthreads<TA>()) k_apply3(const FTile* __restri
   }
 }
 
-template <typename TA, typename TV, typename TC, int M, int T>
+template <typename TA, typename TV, typename TC, int M, int T, bool SIG>
 static void apply3_one(hipStream_t st, const FTile* tiles, int nb, FGeom g, const LInst* li, CIdx ci, const TV* u,
                        const TC* c, TV* out, const TV* bvec, TV* x, TV* r, TV* d, const TV* dinv, int cheb_step,
-                       double* partial, size_t lds, hipEvent_t e0, hipEvent_t e1) {
+                       double* partial, size_t lds, hipEvent_t e0, hipEvent_t e1, const TC* f, const TC* w) {
   // Raise the dynamic-LDS limit of this instantiation on the current device
   // to the largest size requested so far (a host call, kept out of the
   // per-launch path).
@@ -644,62 +654,79 @@ static void apply3_one(hipStream_t st, const FTile* tiles, int nb, FGeom g, cons
   dev = dev < 0 || dev >= 64 ? 0 : dev;
   if (lds > granted[dev]) {
     const size_t want = std::max<size_t>(lds, 96 * 1024);
-    (void)hipFuncSetAttribute((const void*)k_apply3<TA, TV, TC, M, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)want);
+    (void)hipFuncSetAttribute((const void*)k_apply3<TA, TV, TC, M, T, SIG>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)want);
     granted[dev] = want;
   }
   if (e0 && e1)   // timed: the events take the dispatch's own start and end times
-    hipExtLaunchKernelGGL((k_apply3<TA, TV, TC, M, T>), dim3((unsigned)nb), dim3((unsigned)g.nthr), lds, st, e0, e1, 0,
-                          tiles, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial);
+    hipExtLaunchKernelGGL((k_apply3<TA, TV, TC, M, T, SIG>), dim3((unsigned)nb), dim3((unsigned)g.nthr), lds, st, e0,
+                          e1, 0, tiles, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial, f, w);
   else
-    hipLaunchKernelGGL((k_apply3<TA, TV, TC, M, T>), dim3((unsigned)nb), dim3((unsigned)g.nthr), lds, st, tiles, g, li, ci,
-                       u, c, out, bvec, x, r, d, dinv, cheb_step, partial);
+    hipLaunchKernelGGL((k_apply3<TA, TV, TC, M, T, SIG>), dim3((unsigned)nb), dim3((unsigned)g.nthr), lds, st, tiles,
+                       g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial, f, w);
 }
 
 template <typename TA, typename TV, typename TC, int M>
 static void apply3_mode(hipStream_t st, const FTile* tiles, int nb, FGeom g, const LInst* li, CIdx ci, const TV* u,
                         const TC* c, TV* out, const TV* bvec, TV* x, TV* r, TV* d, const TV* dinv, int cheb_step,
-                        double* partial, size_t lds, hipEvent_t e0, hipEvent_t e1) {
+                        double* partial, size_t lds, hipEvent_t e0, hipEvent_t e1, const TC* f, const TC* w) {
   // (the FP64 dot-product pass has no unrolled variant: it would not fit the
-  // register file)
+  // register file; right-hand-side terms exist for the FP64 residual only)
   constexpr bool unroll = !(sizeof(TA) == 8 && M == G_STORE_DOT);
+  constexpr bool rhs = sizeof(TA) == 8 && M == G_RESID;
+  if constexpr (rhs) {
+    if (f && w) {
+      if (g.nt == 32)
+        apply3_one<TA, TV, TC, M, 32, true>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step,
+                                            partial, lds, e0, e1, f, w);
+      else
+        apply3_one<TA, TV, TC, M, 0, true>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step,
+                                           partial, lds, e0, e1, f, w);
+      return;
+    }
+  }
+  if (f || w) throw std::string("fused operator: right-hand-side terms only in the FP64 residual");
   if (unroll && g.nt == 32)
-    apply3_one<TA, TV, TC, M, unroll ? 32 : 0>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step,
-                                                partial, lds, e0, e1);
+    apply3_one<TA, TV, TC, M, unroll ? 32 : 0, false>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv,
+                                                       cheb_step, partial, lds, e0, e1, nullptr, nullptr);
   else
-    apply3_one<TA, TV, TC, M, 0>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial, lds,
-                                 e0, e1);
+    apply3_one<TA, TV, TC, M, 0, false>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial,
+                                        lds, e0, e1, nullptr, nullptr);
 }
 
 template <typename TA, typename TV, typename TC>
 void launch_apply3(hipStream_t st, const FTile* tiles, int nb, FGeom g, const LInst* li, CIdx ci, const TV* u,
                    const TC* c, int mode, TV* out, const TV* bvec, TV* x, TV* r, TV* d, const TV* dinv,
-                   int cheb_step, double* partial, hipEvent_t e0, hipEvent_t e1) {
+                   int cheb_step, double* partial, hipEvent_t e0, hipEvent_t e1, const TC* f, const TC* w) {
   if (nb <= 0) return;
   const size_t lds = sizeof(TA) * (kFRing * (size_t)g.uplane + 16 * (size_t)g.qplane);   // qplane: 4-value slots x 4
   switch (mode) {
     case G_STORE:
-      apply3_mode<TA, TV, TC, G_STORE>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial, lds, e0, e1);
+      apply3_mode<TA, TV, TC, G_STORE>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial,
+                                       lds, e0, e1, f, w);
       break;
     case G_RESID:
-      apply3_mode<TA, TV, TC, G_RESID>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial, lds, e0, e1);
+      apply3_mode<TA, TV, TC, G_RESID>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial,
+                                       lds, e0, e1, f, w);
       break;
     case G_CHEB:
-      apply3_mode<TA, TV, TC, G_CHEB>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial, lds, e0, e1);
+      apply3_mode<TA, TV, TC, G_CHEB>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial,
+                                      lds, e0, e1, f, w);
       break;
     default:
-      apply3_mode<TA, TV, TC, G_STORE_DOT>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial,
-                                           lds, e0, e1);
+      apply3_mode<TA, TV, TC, G_STORE_DOT>(st, tiles, nb, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step,
+                                           partial, lds, e0, e1, f, w);
       break;
   }
 }
 
 template void launch_apply3<float, float, float>(hipStream_t, const FTile*, int, FGeom, const LInst*, CIdx,
                                                  const float*, const float*, int, float*, const float*, float*,
-                                                 float*, float*, const float*, int, double*, hipEvent_t, hipEvent_t);
+                                                 float*, float*, const float*, int, double*, hipEvent_t, hipEvent_t,
+                                                 const float*, const float*);
 template void launch_apply3<double, double, float>(hipStream_t, const FTile*, int, FGeom, const LInst*, CIdx,
                                                    const double*, const float*, int, double*, const double*, double*,
                                                    double*, double*, const double*, int, double*, hipEvent_t,
-                                                   hipEvent_t);
+                                                   hipEvent_t, const float*, const float*);
 
 }  // namespace mpde

@@ -75,15 +75,18 @@ __host__ __device__ inline FSpan fspan(int x0, int T, int n, int per) {
   return s;
 }
 
-// y = S u (no right-hand-side terms) with the epilogue of `mode`
-// (GatherMode); every instance of the tile table must have periodic x and y
-// axes and a non-periodic time axis of at least five points, and the table
-// must be cut for at most fthreads<TA>() threads (g.nthr per block).  Instantiated for FP32 (all modes)
-// and FP64 (vectors and arithmetic in FP64, coefficients FP32).  With events
-// e0, e1 the launch records the dispatch's start and end time in them.
+// y = S u with the epilogue of `mode` (GatherMode); with f and w (level-0
+// source and boundary values; FP64 residual only) y = A_u^T Pi (A_u u - d),
+// the right-hand-side terms included.  Every instance of the tile table must
+// have periodic x and y axes and a non-periodic time axis of at least five
+// points, and the table must be cut for at most fthreads<TA>() threads
+// (g.nthr per block).  Instantiated for FP32 (all modes) and FP64 (vectors
+// and arithmetic in FP64, coefficients FP32).  With events e0, e1 the launch
+// records the dispatch's start and end time in them.
 template <typename TA, typename TV, typename TC>
 void launch_apply3(hipStream_t st, const FTile* tiles, int nb, FGeom g, const LInst* li, CIdx ci, const TV* u,
                    const TC* c, int mode, TV* out, const TV* bvec, TV* x, TV* r, TV* d, const TV* dinv,
-                   int cheb_step, double* partial, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+                   int cheb_step, double* partial, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr,
+                   const TC* f = nullptr, const TC* w = nullptr);
 
 }  // namespace mpde
