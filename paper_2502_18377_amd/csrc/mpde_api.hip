@@ -832,8 +832,10 @@ struct Solver {
     }
   }
 
-  // x = V-cycle(b) on level l (x and b are level-l vectors).
-  void vcycle(int l, TV* b, TV* x) {
+  // x = V-cycle(b) on level l (x and b are level-l vectors).  `started`:
+  // the Chebyshev start vectors of level l (x = 0, r = b, d) were written by
+  // the restriction that produced b.
+  void vcycle(int l, TV* b, TV* x, bool started = false) {
     Level& L = P->lv[l];
     const int nu = P->opt.nu;
     if (!L.cinst64.empty())
@@ -843,12 +845,13 @@ struct Solver {
     if (!L.cinstg.empty()) launch_bb_solve<TV>(st, (int)L.cinstg.size(), L.d_cinstg, L.d, V(P->Sinv), b, x);
     if (L.smooth.nb() == 0) return;
     const Table& t = L.smooth;
-    launch_cheb_init<TV>(st, t.d, t.nb(), L.d, b, V(L.dinv), x, V(L.r), V(L.dd));
+    if (!started) launch_cheb_init<TV>(st, t.d, t.nb(), L.d, b, V(L.dinv), x, V(L.r), V(L.dd));
     chebyshev(l, x, nu);
     Level& Cc = P->lv[l + 1];
-    launch_restrict<TV>(D, st, Cc.all.d, Cc.all.nb(), L.d, Cc.d, V(L.r), V(Cc.b));
+    launch_restrict<TV>(D, st, Cc.all.d, Cc.all.nb(), L.d, Cc.d, V(L.r), V(Cc.b), V(Cc.dinv), V(Cc.x), V(Cc.r),
+                        V(Cc.dd));
     if (use_net && P->net && l + 1 == P->net_level) learned(l + 1, V(Cc.b), V(Cc.x));
-    else vcycle(l + 1, V(Cc.b), V(Cc.x));
+    else vcycle(l + 1, V(Cc.b), V(Cc.x), true);
     launch_prolong_add<TV>(D, st, t.d, t.nb(), L.d, Cc.d, V(Cc.x), x);
     op(l, t, x, G_RESID, V(L.r), b, nullptr, nullptr, V(L.dd), 0, nullptr);
     chebyshev(l, x, nu);
@@ -1004,19 +1007,22 @@ struct Solver {
   // FP64 residual r64 = rhs - S u64 on level 0, and ||r64||^2 per instance
   // into rn2 (adjoint: rhs = ghat, sigma = 0; forward: sigma = 1, rhs = g).
   // The forward right side A_u^T Pi d is the residual at u = 0: the first
-  // residual of a solve (zero_u) evaluates it with the right-side terms and
-  // keeps it in rhs64; later ones, and every adjoint one, are one fused FP64
-  // pass r = rhs - S u where the level has a fused tile table.
+  // residual of a solve (zero_u) is the operator pass with the right-side
+  // terms and is kept in rhs64; later ones, and every adjoint one, are the
+  // pass r = rhs - S u.  One fused FP64 pass where the level has a fused
+  // tile table, else the two-pass kernels.
   void residual64(bool adjoint, double* u64, bool zero_u) {
     Level& L0 = P->lv[0];
     const Table& t = L0.all;
     const FTab& f = L0.fall64;
+    const bool first = !adjoint && zero_u;
     bool done = false;
     if constexpr (std::is_same<TC, float>::value) {
-      if (P->opt.fused && f.ok && (adjoint || !zero_u)) {
+      if (P->opt.fused && f.ok) {
         launch_apply3<double, double, float>(st, f.d, f.nb(), f.g, L0.d, P->ci, u64, C(L0.coef), G_RESID, P->r64,
-                                             adjoint ? P->ghat : P->rhs64, nullptr, nullptr, nullptr, nullptr, 0,
-                                             nullptr);
+                                             adjoint ? P->ghat : (first ? nullptr : P->rhs64), nullptr, nullptr,
+                                             nullptr, nullptr, 0, nullptr, nullptr, nullptr,
+                                             first ? C(P->f) : nullptr, first ? C(P->w) : nullptr);
         done = true;
       }
     }
@@ -1026,9 +1032,9 @@ struct Solver {
       launch_gather<double, double, TC>(D, st, t.d, t.nb(), L0.d, P->ci, u64, P->g64, C(L0.coef), C(P->w),
                                         adjoint ? 0 : 1, G_RESID, P->r64, adjoint ? P->ghat : nullptr, nullptr,
                                         nullptr, nullptr, nullptr, 0, nullptr);
-      if (!adjoint && zero_u)
-        HIPCHK(hipMemcpyAsync(P->rhs64, P->r64, (size_t)L0.npts * sizeof(double), hipMemcpyDeviceToDevice, st));
     }
+    if (first)
+      HIPCHK(hipMemcpyAsync(P->rhs64, P->r64, (size_t)L0.npts * sizeof(double), hipMemcpyDeviceToDevice, st));
     launch_dot<double, double>(st, t.d, t.nb(), L0.d, P->r64, P->r64, P->partial);
     finish(t, P->rn2);
   }
@@ -1199,9 +1205,27 @@ struct Solver {
       auto* dbo = (long long*)upload(bo.data(), bo.size() * sizeof(long long));
       auto* dwk = (Work*)upload(wk.data(), wk.size() * sizeof(Work));
       launch_set_probe(st, dvq, dpc, dps, (int)vq.size(), ncolor, U);
-      launch_gamma<double, double, TC>(D, st, dwk, (int)wk.size(), dvq, P->ci, U, C(L.coef), C(P->f), 0, GM);
-      launch_gather<double, double, TC>(D, st, dwk, (int)wk.size(), dvq, P->ci, U, GM, C(L.coef), C(P->w), 0,
-                                        G_STORE, Y, nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr);
+      // responses Y = S U of the probe vectors: one fused FP64 pass over the
+      // probe instances where the level's shape allows, else the two-pass
+      // kernels
+      bool probed = false;
+      if constexpr (std::is_same<TC, float>::value) {
+        if (P->opt.fused) {
+          FTab ft;
+          make_ftab(ft, vq, (int)vq.size(), std::vector<int>(vq.size(), 1), D, kFThreads64, sizeof(double));
+          if (ft.ok) {
+            auto* dt = (FTile*)upload(ft.h.data(), ft.h.size() * sizeof(FTile));
+            launch_apply3<double, double, float>(st, dt, ft.nb(), ft.g, dvq, P->ci, U, C(L.coef), G_STORE, Y,
+                                                 nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr);
+            probed = true;
+          }
+        }
+      }
+      if (!probed) {
+        launch_gamma<double, double, TC>(D, st, dwk, (int)wk.size(), dvq, P->ci, U, C(L.coef), C(P->f), 0, GM);
+        launch_gather<double, double, TC>(D, st, dwk, (int)wk.size(), dvq, P->ci, U, GM, C(L.coef), C(P->w), 0,
+                                          G_STORE, Y, nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr);
+      }
       launch_extract_band(st, dwk, (int)wk.size(), dvq, dpc, dps, dbo, ncolor, Y, LB);
       HIPCHK(hipStreamSynchronize(st));
     }

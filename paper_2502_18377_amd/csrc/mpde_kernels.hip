@@ -499,10 +499,14 @@ __device__ __forceinline__ Tap2 prolong_taps(int i, int ncn, int per, bool halve
 // Restriction of fine residuals to coarse points: rc = P^T rf / 2^k, k =
 // number of halved axes.  Axis 0 (time) is never halved, so the stencil is
 // the tensor product of the two (or one) spatial axes.
+// With xc != null the coarse level's Chebyshev start (as k_cheb_init) is
+// written too, on instances for which the coarse level is smoothed (not
+// their coarsest): xc = 0, r = rc, d = D^-1 rc / theta.
 template <int D, typename TV>
 __global__ void __launch_bounds__(kBlock) k_restrict(const Work* __restrict__ work, const LInst* __restrict__ lf,
                                                      const LInst* __restrict__ lc, const TV* __restrict__ rf,
-                                                     TV* __restrict__ rc) {
+                                                     TV* __restrict__ rc, const TV* __restrict__ dinv,
+                                                     TV* __restrict__ xc, TV* __restrict__ r0, TV* __restrict__ d0) {
   const Work wk = work[blockIdx.x];
   const LInst& C = lc[wk.inst];
   const LInst& F = lf[wk.inst];
@@ -527,7 +531,14 @@ __global__ void __launch_bounds__(kBlock) k_restrict(const Work* __restrict__ wo
       acc += a1.w[u] * s;
     }
   }
-  rc[C.voff + jc] = (TV)(acc * (1.f / (float)(1 << C.ncoarsened)));
+  const TV v = (TV)(acc * (1.f / (float)(1 << C.ncoarsened)));
+  const long long g = C.voff + jc;
+  rc[g] = v;
+  if (xc && !C.coarsest) {
+    xc[g] = (TV)0;
+    r0[g] = v;
+    d0[g] = (TV)((double)dinv[g] * (double)v / C.cheb_theta);
+  }
 }
 
 // Prolongation and correction x_f += P e_c over fine points.
@@ -1463,10 +1474,10 @@ void launch_cheb_init(hipStream_t st, const Work* w, int nb, const LInst* li, co
 
 template <typename TV>
 void launch_restrict(int D, hipStream_t st, const Work* w, int nb, const LInst* lf, const LInst* lc, const TV* rf,
-                     TV* rc) {
+                     TV* rc, const TV* dinv, TV* xc, TV* r0, TV* d0) {
   if (nb <= 0) return;
-  if (D == 2) hipLaunchKernelGGL((k_restrict<2, TV>), GRID(nb), w, lf, lc, rf, rc);
-  else hipLaunchKernelGGL((k_restrict<3, TV>), GRID(nb), w, lf, lc, rf, rc);
+  if (D == 2) hipLaunchKernelGGL((k_restrict<2, TV>), GRID(nb), w, lf, lc, rf, rc, dinv, xc, r0, d0);
+  else hipLaunchKernelGGL((k_restrict<3, TV>), GRID(nb), w, lf, lc, rf, rc, dinv, xc, r0, d0);
 }
 
 template <typename TV>
@@ -1895,7 +1906,7 @@ INST_TV_TC(double, double, double)
   template void launch_cheb_init<TV>(hipStream_t, const Work*, int, const LInst*, const TV*, const TV*, TV*, TV*, \
                                      TV*);                                                                        \
   template void launch_restrict<TV>(int, hipStream_t, const Work*, int, const LInst*, const LInst*, const TV*,    \
-                                    TV*);                                                                         \
+                                    TV*, const TV*, TV*, TV*, TV*);                                               \
   template void launch_prolong_add<TV>(int, hipStream_t, const Work*, int, const LInst*, const LInst*, const TV*, \
                                        TV*);                                                                      \
   template void launch_convert_dense<TV>(hipStream_t, const double*, TV*, long long);                             \

@@ -20,7 +20,7 @@ void launch_cheb_init(hipStream_t st, const Work* w, int nb, const LInst* li, co
                       TV* r, TV* d);
 template <typename TV>
 void launch_restrict(int D, hipStream_t st, const Work* w, int nb, const LInst* lf, const LInst* lc, const TV* rf,
-                     TV* rc);
+                     TV* rc, const TV* dinv = nullptr, TV* xc = nullptr, TV* r0 = nullptr, TV* d0 = nullptr);
 template <typename TV>
 void launch_prolong_add(int D, hipStream_t st, const Work* w, int nb, const LInst* lf, const LInst* lc,
                         const TV* ec, TV* xf);
