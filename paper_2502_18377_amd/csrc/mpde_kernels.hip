@@ -1548,10 +1548,12 @@ __global__ void __launch_bounds__(kBlock) k_bb_solve64(const int* __restrict__ i
   const TV* B = bvec + L.voff;
   TV* X = xvec + L.voff;
   // The five blocks of a plane (k = 0: the diagonal-block inverse, k = 1..4
-  // the sub-diagonal blocks) are loaded one plane ahead into register sets
-  // indexed by plane parity; each loop is unrolled by two so that the sets
-  // keep fixed registers.
-  TV pre[2][5][CW];
+  // the sub-diagonal blocks) are loaded DEP planes ahead into DEP + 1
+  // register sets used in rotation (two planes ahead for FP32 factors; the
+  // FP64 sets are twice as large, so one plane); the loops are unrolled by
+  // DEP + 1 so that every set keeps fixed registers.
+  constexpr int DEP = sizeof(TV) == 4 ? 2 : 1;
+  TV pre[DEP + 1][5][CW];
   // (a thread's 16 entries of a block row are contiguous and 16-byte
   // aligned: block offsets are multiples of 4 elements)
   auto load_fwd = [&](int t, TV(&d)[5][CW]) {
@@ -1576,7 +1578,7 @@ __global__ void __launch_bounds__(kBlock) k_bb_solve64(const int* __restrict__ i
 #pragma unroll
         for (int q = 0; q < CW; ++q) s -= (double)cur[k][q] * yk[q];
       }
-    load_fwd(t + 1, nxt);
+    load_fwd(t + DEP, nxt);
     s += __shfl_xor(s, 1, 64);
     s += __shfl_xor(s, 2, 64);
     if (h == 0) acc[r] = s;
@@ -1589,10 +1591,13 @@ __global__ void __launch_bounds__(kBlock) k_bb_solve64(const int* __restrict__ i
     if (h == 0) ys[t * M + r] = v;
     __syncthreads();
   };
-  load_fwd(0, pre[0]);
-  for (int t = 0; t < T; t += 2) {
-    fwd(t, pre[0], pre[1]);
-    if (t + 1 < T) fwd(t + 1, pre[1], pre[0]);
+#pragma unroll
+  for (int i = 0; i < DEP; ++i) load_fwd(i, pre[i]);
+  for (int t = 0; t < T; t += DEP + 1) {
+    // plane t + i uses set i and refills set (i + DEP) mod (DEP + 1)
+#pragma unroll
+    for (int i = 0; i <= DEP; ++i)
+      if (t + i < T) fwd(t + i, pre[i], pre[(i + DEP) % (DEP + 1)]);
   }
   // backward: x_t = Dinv_t^T (y_t - sum_k L[t+k][k]^T x_{t+k}); thread (r, h)
   // accumulates column r over rows h*16..h*16+15 of each block.
@@ -1615,7 +1620,7 @@ __global__ void __launch_bounds__(kBlock) k_bb_solve64(const int* __restrict__ i
 #pragma unroll
         for (int q = 0; q < CW; ++q) s -= (double)cur[k][q] * xk[q];
       }
-    load_bwd(t - 1, nxt);
+    load_bwd(t - DEP, nxt);
     s += __shfl_xor(s, 1, 64);
     s += __shfl_xor(s, 2, 64);
     if (h == 0) acc[r] = s;
@@ -1628,10 +1633,12 @@ __global__ void __launch_bounds__(kBlock) k_bb_solve64(const int* __restrict__ i
     if (h == 0) { ys[t * M + r] = v; X[(long long)t * M + r] = (TV)v; }
     __syncthreads();
   };
-  load_bwd(T - 1, pre[0]);
-  for (int t = T - 1; t >= 0; t -= 2) {
-    bwd(t, pre[0], pre[1]);
-    if (t - 1 >= 0) bwd(t - 1, pre[1], pre[0]);
+#pragma unroll
+  for (int i = 0; i < DEP; ++i) load_bwd(T - 1 - i, pre[i]);
+  for (int t = T - 1; t >= 0; t -= DEP + 1) {
+#pragma unroll
+    for (int i = 0; i <= DEP; ++i)
+      if (t - i >= 0) bwd(t - i, pre[i], pre[(i + DEP) % (DEP + 1)]);
   }
 }
 

@@ -79,11 +79,14 @@ def _rows(d):
 def _mode(kernel_name):
     """Key of a k_apply3 instantiation: its operator mode (fourth template
     argument) as in Problem.time_operator, i.e. "4" for the FP64 residual
-    pass (arithmetic type double); None for other kernels."""
+    pass (arithmetic type double); "fp64_<mode>" for other FP64 passes;
+    None for other kernels."""
     if "k_apply3<" not in kernel_name:
         return None
     args = [a.strip() for a in kernel_name.split("k_apply3<")[1].split(">")[0].split(",")]
-    return "4" if args[0] == "double" else args[3]
+    if args[0] == "double":   # FP64: the outer residual is mode 4; other FP64 passes (probing) apart
+        return "4" if args[3] == "1" else "fp64_" + args[3]
+    return args[3]
 
 
 def _per_dispatch(rows, match):
