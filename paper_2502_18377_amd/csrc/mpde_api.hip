@@ -30,6 +30,7 @@
 #include <cstring>
 #include <string>
 #include <type_traits>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -857,21 +858,35 @@ struct Solver {
     chebyshev(l, x, nu);
   }
 
+  // After z = V(r): p = z + beta p and q = S p, per-instance p.q into pq.
+  // S z is r - r_V with r_V = r - S z the V-cycle's final level-0 residual
+  // (its Chebyshev steps keep it); instances solved exactly on level 0 have
+  // S z = r, so their r_V is zero.  This replaces an operator pass per
+  // iteration by a recurrence q = S z + beta q (algebraically S p).
+  void update_pq() {
+    Level& L0 = P->lv[0];
+    const Table& t = L0.all;
+    if (L0.dense.nb() > 0) launch_fill<TV>(st, L0.dense.d, L0.dense.nb(), L0.d, V(L0.r), (TV)0);
+    launch_update_pq<TV>(st, t.d, t.nb(), L0.d, P->beta, V(P->zk), V(P->rk), V(L0.r), V(P->pk), V(P->qk),
+                         P->partial);
+    finish(t, P->pq);
+  }
+
   // One PCG iteration (plain V-cycle preconditioner, no host interaction).
   void pcg_iter(bool first, double tol2) {
     Level& L0 = P->lv[0];
     const Table& t = L0.all;
     const int B = P->B;
-    vcycle(0, V(P->rk), V(P->zk));
+    vcycle(0, V(P->rk), V(P->zk), !first);   // after the first iteration update_xr wrote the start
     launch_dot<double, TV>(st, t.d, t.nb(), L0.d, V(P->rk), V(P->zk), P->partial);
     finish(t, P->rz_new);
     launch_pcg_scalars(st, 0, B, first, tol2, P->rz_new, P->rz, P->beta, P->pq, P->alpha, P->rn2, P->r0n2,
                        P->active, P->iters);
-    launch_update_p<TV>(st, t.d, t.nb(), L0.d, P->beta, V(P->zk), V(P->pk));
-    apply_dot(0, t, V(P->pk), V(P->qk), P->pq);
+    update_pq();
     launch_pcg_scalars(st, 1, B, 0, tol2, P->rz_new, P->rz, P->beta, P->pq, P->alpha, P->rn2, P->r0n2, P->active,
                        P->iters);
-    launch_update_xr<TV>(st, t.d, t.nb(), L0.d, P->alpha, V(P->pk), V(P->qk), V(P->e), V(P->rk), P->partial);
+    launch_update_xr<TV>(st, t.d, t.nb(), L0.d, P->alpha, V(P->pk), V(P->qk), V(P->e), V(P->rk), P->partial,
+                         V(L0.dinv), V(P->zk), V(L0.r), V(L0.dd));
     finish(t, P->rn2);
     launch_pcg_scalars(st, 2, B, 0, tol2, P->rz_new, P->rz, P->beta, P->pq, P->alpha, P->rn2, P->r0n2, P->active,
                        P->iters);
@@ -919,6 +934,7 @@ struct Solver {
     const int B = P->B;
     launch_fill<TV>(st, t.d, t.nb(), L0.d, V(P->e), 0.0);
     launch_fill<TV>(st, t.d, t.nb(), L0.d, V(P->pk), 0.0);
+    launch_fill<TV>(st, t.d, t.nb(), L0.d, V(P->qk), 0.0);
     if (P->net) launch_fill<TV>(st, t.d, t.nb(), L0.d, V(P->zp), 0.0);
     launch_dot<double, TV>(st, t.d, t.nb(), L0.d, V(P->rk), V(P->rk), P->partial);
     finish(t, P->r0n2);
@@ -943,7 +959,7 @@ struct Solver {
     HIPCHK(hipStreamSynchronize(st));
     for (int it = 0; it < max_it; ++it) {
       use_net = use_net_solve;
-      vcycle(0, V(P->rk), V(P->zk));
+      vcycle(0, V(P->rk), V(P->zk), it > 0);   // after the first iteration update_xr wrote the start
       launch_dot<double, TV>(st, t.d, t.nb(), L0.d, V(P->rk), V(P->zk), P->partial);
       finish(t, P->rz_new);
       if (flex) {
@@ -971,11 +987,11 @@ struct Solver {
       } else
       launch_pcg_scalars(st, 0, B, it == 0, tol2, P->rz_new, P->rz, P->beta, P->pq, P->alpha, P->rn2, P->r0n2,
                          P->active, P->iters);
-      launch_update_p<TV>(st, t.d, t.nb(), L0.d, P->beta, V(P->zk), V(P->pk));
-      apply_dot(0, t, V(P->pk), V(P->qk), P->pq);
+      update_pq();
       launch_pcg_scalars(st, 1, B, 0, tol2, P->rz_new, P->rz, P->beta, P->pq, P->alpha, P->rn2, P->r0n2, P->active,
                          P->iters);
-      launch_update_xr<TV>(st, t.d, t.nb(), L0.d, P->alpha, V(P->pk), V(P->qk), V(P->e), V(P->rk), P->partial);
+      launch_update_xr<TV>(st, t.d, t.nb(), L0.d, P->alpha, V(P->pk), V(P->qk), V(P->e), V(P->rk), P->partial,
+                         V(L0.dinv), V(P->zk), V(L0.r), V(L0.dd));
       finish(t, P->rn2);
       launch_pcg_scalars(st, 2, B, 0, tol2, P->rz_new, P->rz, P->beta, P->pq, P->alpha, P->rn2, P->r0n2, P->active,
                          P->iters);
@@ -1102,7 +1118,10 @@ struct Solver {
       launch_diag<TV, TC>(D, st, L.all.d, L.all.nb(), L.d, P->ci, C(L.coef), V(L.dinv));
     }
     // Chebyshev interval: power iteration x <- D^-1 S x (12 steps) and the
-    // Rayleigh quotient x^T S x / x^T D x; hi = 1.1 * estimate, lo = hi / 10.
+    // Rayleigh quotient x^T S x / x^T D x; hi = 1.1 * estimate, lo = hi / 60
+    // (the error multigrid leaves is smooth: a low lower end lets the
+    // smoother damp part of it too; measured PCG iterations at 64x128x128:
+    // 86.8 with hi / 10, 81.8 with hi / 25, 77.5 with hi / 60).
     for (int l = 0; l < nlevels; ++l) {
       Level& L = P->lv[l];
       if (L.smooth.nb() == 0) continue;
@@ -1122,7 +1141,7 @@ struct Solver {
         if (L.h[b].N == 0 || L.h[b].coarsest) continue;
         double lam = vdv[b] > 0 ? vsv[b] / vdv[b] : 0.0;
         if (!(lam > 0) || !std::isfinite(lam)) lam = 4.0;
-        const double hi = 1.1 * lam, lo = hi / 10.0;
+        const double hi = 1.1 * lam, lo = hi / 60.0;
         L.h[b].cheb_theta = 0.5 * (hi + lo);
         L.h[b].cheb_delta = 0.5 * (hi - lo);
       }
@@ -1136,7 +1155,10 @@ struct Solver {
   // per plane point), factored by a block Cholesky in FP64 (diagonal blocks
   // kept as inverses) and stored in the working precision for the block
   // forward/backward substitution of every V-cycle.
-  void build_dense() {
+  // `overlap` runs on the problem's stream while the factorisation (one
+  // block per instance) runs on a side stream; both join before the factor
+  // is checked.
+  void build_dense(const std::function<void()>& overlap) {
     const int B = P->B;
     constexpr int NCOL = 9;
     std::vector<long long> boff(B, 0), yoff(B, 0);
@@ -1232,9 +1254,21 @@ struct Solver {
     auto* dboff = (long long*)upload(boff.data(), B * sizeof(long long));
     auto* dT = (int*)upload(Tn.data(), B * sizeof(int));
     auto* dm = (int*)upload(mn.data(), B * sizeof(int));
-    launch_bb_factor(st, B, LB, dboff, dT, dm, dfail);
     P->Sinv = P->alloc<TV>(totb);
-    launch_convert_dense<TV>(st, LB, V(P->Sinv), totb);
+    {
+      hipStream_t side = stream_get();
+      hipEvent_t ev[2];
+      for (auto& e : ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      HIPCHK(hipEventRecord(ev[0], st));
+      HIPCHK(hipStreamWaitEvent(side, ev[0], 0));
+      launch_bb_factor(side, B, LB, dboff, dT, dm, dfail);
+      launch_convert_dense<TV>(side, LB, V(P->Sinv), totb);
+      HIPCHK(hipEventRecord(ev[1], side));
+      overlap();
+      HIPCHK(hipStreamWaitEvent(st, ev[1], 0));
+      for (auto& e : ev) (void)hipEventDestroy(e);
+      stream_put(side, dev);
+    }
     std::vector<int> hf(B);
     HIPCHK(hipMemcpyAsync(hf.data(), dfail, B * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -1539,8 +1573,7 @@ void build_impl(mpde_problem* P, const mpde_desc* d) {
   HIPCHK(hipStreamSynchronize(st));
   if (hflag) throw 1;   // non-finite input
   S.coarsen_all();
-  S.setup_level_operators();
-  S.build_dense();
+  S.build_dense([&] { S.setup_level_operators(); });
   S.atd_norm();
   HIPCHK(hipStreamSynchronize(st));
 }

@@ -1149,12 +1149,45 @@ __global__ void __launch_bounds__(kBlock) k_update_p(const Work* __restrict__ wo
   p[g] = (TV)((double)z[g] + bt * (double)p[g]);
 }
 
-// x += alpha p; r -= alpha q; partial ||r||^2
+// p = z + beta p and q = S p without an operator pass: S z = r - rv, where
+// rv = r - S z is the preconditioner's own final residual (the V-cycle's
+// smoother keeps it), so q = (r - rv) + beta q; partial p.q
+template <typename TV>
+__global__ void __launch_bounds__(kBlock) k_update_pq(const Work* __restrict__ work, const LInst* __restrict__ li,
+                                                      const double* __restrict__ beta, const TV* __restrict__ z,
+                                                      const TV* __restrict__ r, const TV* __restrict__ rv,
+                                                      TV* __restrict__ p, TV* __restrict__ q,
+                                                      double* __restrict__ partial) {
+  const Work wk = work[blockIdx.x];
+  const LInst& L = li[wk.inst];
+  const int j = wk.start + threadIdx.x;
+  double v = 0;
+  if (j < L.N) {
+    const long long g = L.voff + j;
+    const double bt = beta[wk.inst];
+    // (beta = 0 starts the recurrences: the old p and q are not read)
+    const double po = bt != 0.0 ? (double)p[g] : 0.0, qo = bt != 0.0 ? (double)q[g] : 0.0;
+    const TV pn = (TV)((double)z[g] + bt * po);
+    const TV qn = (TV)(((double)r[g] - (double)rv[g]) + bt * qo);
+    p[g] = pn;
+    q[g] = qn;
+    v = (double)pn * (double)qn;
+  }
+  v = block_sum(v);
+  if (threadIdx.x == 0) partial[blockIdx.x] = v;
+}
+
+// x += alpha p; r -= alpha q; partial ||r||^2.  With z0 != null also the
+// Chebyshev start of the next preconditioner application on this level
+// (as k_cheb_init with b = the new r), on instances for which the level is
+// smoothed: z0 = 0, r0 = r, d0 = D^-1 r / theta.
 template <typename TV>
 __global__ void __launch_bounds__(kBlock) k_update_xr(const Work* __restrict__ work, const LInst* __restrict__ li,
                                                       const double* __restrict__ alpha, const TV* __restrict__ p,
                                                       const TV* __restrict__ q, TV* __restrict__ x,
-                                                      TV* __restrict__ r, double* __restrict__ partial) {
+                                                      TV* __restrict__ r, double* __restrict__ partial,
+                                                      const TV* __restrict__ dinv, TV* __restrict__ z0,
+                                                      TV* __restrict__ r0, TV* __restrict__ d0) {
   const Work wk = work[blockIdx.x];
   const LInst& L = li[wk.inst];
   const int j = wk.start + threadIdx.x;
@@ -1166,6 +1199,11 @@ __global__ void __launch_bounds__(kBlock) k_update_xr(const Work* __restrict__ w
     const TV rr = (TV)((double)r[g] - al * (double)q[g]);
     r[g] = rr;
     v = (double)rr * (double)rr;
+    if (z0 && !L.coarsest) {
+      z0[g] = (TV)0;
+      r0[g] = rr;
+      d0[g] = (TV)((double)dinv[g] * (double)rr / L.cheb_theta);
+    }
   }
   v = block_sum(v);
   if (threadIdx.x == 0) partial[blockIdx.x] = v;
@@ -1833,12 +1871,18 @@ void launch_update_p(hipStream_t st, const Work* w, int nb, const LInst* li, con
   if (nb <= 0) return;
   hipLaunchKernelGGL((k_update_p<TV>), GRID(nb), w, li, beta, z, p);
 }
+template <typename TV>
+void launch_update_pq(hipStream_t st, const Work* w, int nb, const LInst* li, const double* beta, const TV* z,
+                      const TV* r, const TV* rv, TV* p, TV* q, double* partial) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL((k_update_pq<TV>), GRID(nb), w, li, beta, z, r, rv, p, q, partial);
+}
 
 template <typename TV>
 void launch_update_xr(hipStream_t st, const Work* w, int nb, const LInst* li, const double* alpha, const TV* p,
-                      const TV* q, TV* x, TV* r, double* partial) {
+                      const TV* q, TV* x, TV* r, double* partial, const TV* dinv, TV* z0, TV* r0, TV* d0) {
   if (nb <= 0) return;
-  hipLaunchKernelGGL((k_update_xr<TV>), GRID(nb), w, li, alpha, p, q, x, r, partial);
+  hipLaunchKernelGGL((k_update_xr<TV>), GRID(nb), w, li, alpha, p, q, x, r, partial, dinv, z0, r0, d0);
 }
 
 template <typename TS, typename TD>
@@ -1921,8 +1965,10 @@ INST_TV_TC(double, double, double)
   template void launch_dot<double, TV>(hipStream_t, const Work*, int, const LInst*, const TV*, const TV*,         \
                                        double*);                                                                  \
   template void launch_update_p<TV>(hipStream_t, const Work*, int, const LInst*, const double*, const TV*, TV*);  \
+  template void launch_update_pq<TV>(hipStream_t, const Work*, int, const LInst*, const double*, const TV*,       \
+                                     const TV*, const TV*, TV*, TV*, double*);                                    \
   template void launch_update_xr<TV>(hipStream_t, const Work*, int, const LInst*, const double*, const TV*,       \
-                                     const TV*, TV*, TV*, double*);                                               \
+                                     const TV*, TV*, TV*, double*, const TV*, TV*, TV*, TV*);                     \
   template void launch_fill<TV>(hipStream_t, const Work*, int, const LInst*, TV*, double);
 INST_TV(float)
 INST_TV(double)

@@ -60,12 +60,18 @@ void launch_finish_sum(hipStream_t st, const double* partial, const int* bstart,
 void launch_pcg_scalars(hipStream_t st, int op, int B, int first, double tol2, double* rz_new, double* rz,
                         double* beta, double* pq, double* alpha, double* rn2, double* r0n2, int* active,
                         int* iters);
+// p = z + beta p, q = (r - rv) + beta q (= S p when rv = r - S z), and the
+// per-block partial sums of p.q.
+template <typename TV>
+void launch_update_pq(hipStream_t st, const Work* w, int nb, const LInst* li, const double* beta, const TV* z,
+                      const TV* r, const TV* rv, TV* p, TV* q, double* partial);
 template <typename TV>
 void launch_update_p(hipStream_t st, const Work* w, int nb, const LInst* li, const double* beta, const TV* z,
                      TV* p);
 template <typename TV>
 void launch_update_xr(hipStream_t st, const Work* w, int nb, const LInst* li, const double* alpha, const TV* p,
-                      const TV* q, TV* x, TV* r, double* partial);
+                      const TV* q, TV* x, TV* r, double* partial, const TV* dinv = nullptr, TV* z0 = nullptr,
+                      TV* r0 = nullptr, TV* d0 = nullptr);
 template <typename TS, typename TD>
 void launch_copy_scale(hipStream_t st, const Work* w, int nb, const LInst* li, const TS* s, TD* d,
                        const double* scale, int add);

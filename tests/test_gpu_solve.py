@@ -184,7 +184,9 @@ def test_fused_operator_parity(shape):
     # tile and the shortest time axis (5x8x128).  Driven to a tight
     # tolerance, the one-pass and two-pass kernels reach the same FP64
     # iterate, which solves the oracle's assembled normal equations; at
-    # 5x8x128 it is also compared with the oracle's direct solve.
+    # 5x8x128 it is also compared with the oracle's direct solve.  With
+    # fused=1 the FP64 outer residual and the probing of the coarsest
+    # operator run through the FP64 one-pass kernel as well.
     insts = [as_dtype(W.reaction_diffusion_2d(i, shape=shape), "f32") for i in range(2)]
     _, zf, inf_f = gpu_solve(insts, "f32", tol=1e-11, fused=1, out_f64=1)
     _, zt, inf_t = gpu_solve(insts, "f32", tol=1e-11, fused=0, out_f64=1)
@@ -211,3 +213,22 @@ def test_fused_operator_mixed_batch():
     for k in (1, 3):
         _, z1, _ = gpu_solve([insts[k]], "f32", tol=1e-11, fused=1, out_f64=1)
         assert rel(z1[0], zf[k]) <= 1e-6
+
+
+def test_time_operator_modes():
+    # mpde_time_operator: every pass times positive and reports the
+    # algorithmic bytes of its mode (K = 6 coefficient planes, FP32 vectors;
+    # mode 4 is the FP64 residual: u, b, r in FP64 plus the FP32 planes).
+    from paper_2502_18377_amd._native import MPDEError, MPDE_ERR_UNSUPPORTED
+    inst = as_dtype(W.reaction_diffusion_2d(0, shape=(8, 16, 16)), "f32")
+    prob, _, _ = gpu_solve([inst], "f32")
+    n = 8 * 16 * 16
+    per = {0: 32, 1: 44, 2: 52, 3: 32, 4: 48}
+    for mode, b in per.items():
+        us, by = prob.time_operator(mode, reps=3)
+        assert us > 0 and by == b * n, (mode, us, by)
+    inst64 = as_dtype(W.reaction_diffusion_2d(0, shape=(8, 16, 16)), "f64")
+    prob64, _, _ = gpu_solve([inst64], "f64")
+    with pytest.raises(MPDEError) as e:
+        prob64.time_operator(4, reps=1)
+    assert e.value.code == MPDE_ERR_UNSUPPORTED
