@@ -1572,6 +1572,22 @@ void launch_bb_factor(hipStream_t st, int nmat, double* Lb, const long long* bof
 // columns h*16..h*16+15 of row r in every block; the four off-diagonal
 // blocks of the next step are prefetched into registers while the current
 // step's reductions run.
+// Sum over the four lanes of a quad (lanes 4i..4i+3) by two DPP quad
+// permutations (lane ^ 1, then lane ^ 2) on the two halves of the double:
+// register moves within the wavefront, no LDS round trip.
+template <int CTRL>
+__device__ __forceinline__ double dpp_quad(double v) {
+  int2 h = __builtin_bit_cast(int2, v);
+  h.x = __builtin_amdgcn_update_dpp(0, h.x, CTRL, 0xF, 0xF, false);
+  h.y = __builtin_amdgcn_update_dpp(0, h.y, CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, h);
+}
+__device__ __forceinline__ double quad_sum(double v) {
+  v += dpp_quad<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_quad<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  return v;
+}
+
 template <typename TV>
 __global__ void __launch_bounds__(kBlock) k_bb_solve64(const int* __restrict__ inst_list,
                                                        const LInst* __restrict__ li, const TV* __restrict__ Lb,
@@ -1592,92 +1608,112 @@ __global__ void __launch_bounds__(kBlock) k_bb_solve64(const int* __restrict__ i
   // DEP + 1 so that every set keeps fixed registers.
   constexpr int DEP = sizeof(TV) == 4 ? 2 : 1;
   TV pre[DEP + 1][5][CW];
+  TV bpre[DEP + 1];
+  // Every load is unconditional: the plane index is clamped to [0, T) and
+  // blocks that a plane does not use (k > t, or past the ends) are loaded
+  // from valid storage and ignored, so no load sits in a branch and the
+  // compiler's wait counts stay partial (a conditional load or a store in
+  // the loop makes it wait for every load in flight at each barrier).
   // (a thread's 16 entries of a block row are contiguous and 16-byte
   // aligned: block offsets are multiples of 4 elements)
-  auto load_fwd = [&](int t, TV(&d)[5][CW]) {
+  auto clampt = [&](int t) { return t < 0 ? 0 : (t >= T ? T - 1 : t); };
+  auto load_fwd = [&](int t, TV(&d)[5][CW], TV& bt) {
+    const int tc = clampt(t);
 #pragma unroll
     for (int k = 0; k <= 4; ++k) {
-      if (t - k >= 0 && t < T) {
-        const uint4* Lk = reinterpret_cast<const uint4*>(Lb + bb_at(base, t, k, M) + r * M + c0);
+      const uint4* Lk = reinterpret_cast<const uint4*>(Lb + bb_at(base, tc, k, M) + r * M + c0);
 #pragma unroll
-        for (int v = 0; v < CW * (int)sizeof(TV) / 16; ++v) {
-          const uint4 x = Lk[v];
-          __builtin_memcpy(&d[k][v * 16 / sizeof(TV)], &x, 16);
-        }
+      for (int v = 0; v < CW * (int)sizeof(TV) / 16; ++v) {
+        const uint4 x = Lk[v];
+        __builtin_memcpy(&d[k][v * 16 / sizeof(TV)], &x, 16);
       }
     }
+    bt = B[(long long)tc * M + r];
   };
-  auto fwd = [&](int t, TV(&cur)[5][CW], TV(&nxt)[5][CW]) {
-    double s = (h == 0) ? (double)B[(long long)t * M + r] : 0.0;
+  // (one accumulator per block and two for the diagonal product keep the
+  // dependent FMA chains short)
+  auto fwd = [&](int t, TV(&cur)[5][CW], TV bt, TV(&nxt)[5][CW], TV& nbt) {
+    double sk[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 1; k <= 4; ++k)
       if (t - k >= 0) {
         const double* yk = ys + (t - k) * M + c0;
 #pragma unroll
-        for (int q = 0; q < CW; ++q) s -= (double)cur[k][q] * yk[q];
+        for (int q = 0; q < CW; ++q) sk[k - 1] = fma(-(double)cur[k][q], yk[q], sk[k - 1]);
       }
-    load_fwd(t + DEP, nxt);
-    s += __shfl_xor(s, 1, 64);
-    s += __shfl_xor(s, 2, 64);
+    load_fwd(t + DEP, nxt, nbt);
+    double s = ((h == 0) ? (double)bt : 0.0) + ((sk[0] + sk[1]) + (sk[2] + sk[3]));
+    s = quad_sum(s);
     if (h == 0) acc[r] = s;
     __syncthreads();
-    double v = 0;
+    double v0 = 0, v1 = 0;
 #pragma unroll
-    for (int q = 0; q < CW; ++q) v += (double)cur[0][q] * acc[c0 + q];   // Dinv lower: upper entries are 0
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
+    for (int q = 0; q < CW; q += 2) {   // Dinv lower: upper entries are 0
+      v0 = fma((double)cur[0][q], acc[c0 + q], v0);
+      v1 = fma((double)cur[0][q + 1], acc[c0 + q + 1], v1);
+    }
+    const double v = quad_sum(v0 + v1);
     if (h == 0) ys[t * M + r] = v;
     __syncthreads();
   };
 #pragma unroll
-  for (int i = 0; i < DEP; ++i) load_fwd(i, pre[i]);
-  for (int t = 0; t < T; t += DEP + 1) {
-    // plane t + i uses set i and refills set (i + DEP) mod (DEP + 1)
+  for (int i = 0; i < DEP; ++i) load_fwd(i, pre[i], bpre[i]);
+  // plane t + i uses set i and refills set (i + DEP) mod (DEP + 1); whole
+  // groups of DEP + 1 planes, then the remaining planes
+  int t = 0;
+  for (; t + DEP < T; t += DEP + 1) {
 #pragma unroll
-    for (int i = 0; i <= DEP; ++i)
-      if (t + i < T) fwd(t + i, pre[i], pre[(i + DEP) % (DEP + 1)]);
+    for (int i = 0; i <= DEP; ++i) fwd(t + i, pre[i], bpre[i], pre[(i + DEP) % (DEP + 1)], bpre[(i + DEP) % (DEP + 1)]);
   }
+#pragma unroll
+  for (int i = 0; i < DEP; ++i)
+    if (t + i < T) fwd(t + i, pre[i], bpre[i], pre[(i + DEP) % (DEP + 1)], bpre[(i + DEP) % (DEP + 1)]);
   // backward: x_t = Dinv_t^T (y_t - sum_k L[t+k][k]^T x_{t+k}); thread (r, h)
-  // accumulates column r over rows h*16..h*16+15 of each block.
+  // accumulates column r over rows h*16..h*16+15 of each block; x overwrites
+  // y in LDS and is written out after the sweep.
   auto load_bwd = [&](int t, TV(&d)[5][CW]) {
 #pragma unroll
     for (int k = 0; k <= 4; ++k) {
-      if (t >= 0 && t + k < T) {
-        const TV* Lk = Lb + bb_at(base, t + k, k, M);
+      const TV* Lk = Lb + bb_at(base, clampt(t + k), k, M);
 #pragma unroll
-        for (int q = 0; q < CW; ++q) d[k][q] = Lk[(c0 + q) * M + r];
-      }
+      for (int q = 0; q < CW; ++q) d[k][q] = Lk[(c0 + q) * M + r];
     }
   };
   auto bwd = [&](int t, TV(&cur)[5][CW], TV(&nxt)[5][CW]) {
-    double s = (h == 0) ? ys[t * M + r] : 0.0;
+    double sk[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 1; k <= 4; ++k)
       if (t + k < T) {
         const double* xk = ys + (t + k) * M + c0;
 #pragma unroll
-        for (int q = 0; q < CW; ++q) s -= (double)cur[k][q] * xk[q];
+        for (int q = 0; q < CW; ++q) sk[k - 1] = fma(-(double)cur[k][q], xk[q], sk[k - 1]);
       }
     load_bwd(t - DEP, nxt);
-    s += __shfl_xor(s, 1, 64);
-    s += __shfl_xor(s, 2, 64);
+    double s = ((h == 0) ? ys[t * M + r] : 0.0) + ((sk[0] + sk[1]) + (sk[2] + sk[3]));
+    s = quad_sum(s);
     if (h == 0) acc[r] = s;
     __syncthreads();
-    double v = 0;
+    double v0 = 0, v1 = 0;
 #pragma unroll
-    for (int q = 0; q < CW; ++q) v += (double)cur[0][q] * acc[c0 + q];
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
-    if (h == 0) { ys[t * M + r] = v; X[(long long)t * M + r] = (TV)v; }
+    for (int q = 0; q < CW; q += 2) {
+      v0 = fma((double)cur[0][q], acc[c0 + q], v0);
+      v1 = fma((double)cur[0][q + 1], acc[c0 + q + 1], v1);
+    }
+    const double v = quad_sum(v0 + v1);
+    if (h == 0) ys[t * M + r] = v;
     __syncthreads();
   };
 #pragma unroll
   for (int i = 0; i < DEP; ++i) load_bwd(T - 1 - i, pre[i]);
-  for (int t = T - 1; t >= 0; t -= DEP + 1) {
+  t = T - 1;
+  for (; t - DEP >= 0; t -= DEP + 1) {
 #pragma unroll
-    for (int i = 0; i <= DEP; ++i)
-      if (t - i >= 0) bwd(t - i, pre[i], pre[(i + DEP) % (DEP + 1)]);
+    for (int i = 0; i <= DEP; ++i) bwd(t - i, pre[i], pre[(i + DEP) % (DEP + 1)]);
   }
+#pragma unroll
+  for (int i = 0; i < DEP; ++i)
+    if (t - i >= 0) bwd(t - i, pre[i], pre[(i + DEP) % (DEP + 1)]);
+  for (int e = tid; e < T * M; e += kBlock) X[e] = (TV)ys[e];
 }
 
 // Specialisation for planes of at most 16 points: one wavefront per
