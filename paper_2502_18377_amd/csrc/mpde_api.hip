@@ -374,11 +374,13 @@ void make_table(Table& t, const std::vector<LInst>& h, int B, const std::vector<
 // per compute unit) where the shapes allow, and then the fewest wavefronts
 // in total: halo rows are evaluated by every tile that needs them, so this
 // minimises the redundant row work.  `esize` is the byte size of the
-// arithmetic type (LDS budget).  Consecutive groups of 8 instances are
+// arithmetic type (LDS budget); `mult` (optional) counts each instance that
+// many times in the choice (instances that stand for several identical
+// ones).  Consecutive groups of 8 instances are
 // interleaved tile by tile, so that with round-robin block dispatch all
 // tiles of one instance (which share halos) run on the same XCD and its L2.
 void make_ftab(FTab& f, const std::vector<LInst>& h, int B, const std::vector<int>& sel, int D, int nth,
-               size_t esize) {
+               size_t esize, const std::vector<long long>* mult = nullptr) {
   f.h.clear();
   f.bstart.assign(B + 1, 0);
   f.ok = false;
@@ -400,17 +402,21 @@ void make_ftab(FTab& f, const std::vector<LInst>& h, int B, const std::vector<in
     long long tiles = 0, waves = 0;
     int uplane = 0, qplane = 0, nthr = 0;
   };
+  // instances grouped by plane shape: a candidate is evaluated once per shape
+  std::map<std::pair<int, int>, long long> shapes;
+  for (int b = 0; b < B; ++b)
+    if (sel[b] && h[b].N > 0) shapes[{h[b].n[1], h[b].n[2]}] += mult ? (*mult)[b] : 1;
   auto cut = [&](int TX, int TY, Cut& c) {
     c = Cut{};
-    for (int b = 0; b < B; ++b) {
-      if (!sel[b] || h[b].N == 0) continue;
-      const LInst& q = h[b];
-      for (int x0 = 0; x0 < q.n[1]; x0 += TX)
-        for (int y0 = 0; y0 < q.n[2]; y0 += TY) {
-          const FSpan X = fspan(x0, TX, q.n[1], 1), Y = fspan(y0, TY, q.n[2], 1);
+    for (const auto& sh : shapes) {
+      const int nx = sh.first.first, ny = sh.first.second;
+      const long long cnt = sh.second;
+      for (int x0 = 0; x0 < nx; x0 += TX)
+        for (int y0 = 0; y0 < ny; y0 += TY) {
+          const FSpan X = fspan(x0, TX, nx, 1), Y = fspan(y0, TY, ny, 1);
           if (X.qn * Y.qn > nth || X.un * Y.un > 2 * nth) return false;
-          c.tiles += 1;
-          c.waves += (X.qn * Y.qn + 63) / 64;
+          c.tiles += cnt;
+          c.waves += cnt * ((X.qn * Y.qn + 63) / 64);
           c.uplane = std::max(c.uplane, X.un * Y.un);
           c.qplane = std::max(c.qplane, X.qs * Y.qs);
           // block size: every row point, and every staged u slot within two per thread
@@ -533,16 +539,8 @@ struct Solver {
   void level_norms(int l, const TV* r) {
     Level& L = P->lv[l];
     launch_dot<double, TV>(st, L.all.d, L.all.nb(), L.d, r, r, P->partial);
-    finish(L.all, P->pq);
-    std::vector<double> n2(P->B), nn(P->B), iv(P->B);
-    HIPCHK(hipMemcpyAsync(n2.data(), P->pq, P->B * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    for (int b = 0; b < P->B; ++b) {
-      nn[b] = std::sqrt(std::max(n2[b], 0.0));
-      iv[b] = nn[b] > 0 ? 1.0 / nn[b] : 0.0;
-    }
-    HIPCHK(hipMemcpyAsync(P->ns.norm, nn.data(), P->B * sizeof(double), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(P->ns.inv, iv.data(), P->B * sizeof(double), hipMemcpyHostToDevice, st));
+    finish(L.all, P->rzp);
+    norms_launch(st, P->B, P->rzp, P->ns.norm, P->ns.inv);
   }
 
   void net_forward(const mpde_net* net) {
@@ -1198,58 +1196,89 @@ struct Solver {
       HIPCHK(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, st));
       return d;
     };
+    auto scratch = [&](size_t bytes) {
+      void* d = dalloc<char>(std::max<size_t>(bytes, 1));
+      fr.v.push_back({d, std::max<size_t>(bytes, 1), dev});
+      return d;
+    };
     for (int l = 0; l < (int)P->lv.size(); ++l) {
       Level& L = P->lv[l];
-      std::vector<LInst> vq;
-      std::vector<int> pc, ps;
-      std::vector<long long> bo;
-      std::vector<Work> wk;
+      // probed instances (their coarsest level is l); the probe descriptors,
+      // work items and tiles are expanded on the device from these
+      std::vector<ProbeSrc> src;
+      std::vector<LInst> reps;
+      std::vector<long long> mult;
       int ncolor = -1;
+      long long nvq = 0, nwk = 0;
       for (int b = 0; b < B; ++b) {
         if (L.h[b].N == 0 || !L.h[b].coarsest) continue;
         const int n = L.h[b].N, plane = mn[b], nc = std::min(L.h[b].n[0], NCOL);
         if (ncolor >= 0 && nc != ncolor)
           throw std::string("mixed time-axis lengths below 9 on one coarsest level are not supported");
         ncolor = nc;
-        for (int c = 0; c < nc; ++c)
-          for (int sp = 0; sp < plane; ++sp) {
-            const int id = (int)vq.size();
-            LInst q = L.h[b];
-            q.voff = yoff[b] + (long long)(c * plane + sp) * n;
-            vq.push_back(q); pc.push_back(c); ps.push_back(sp); bo.push_back(boff[b]);
-            for (int s0 = 0; s0 < n; s0 += kBlock) wk.push_back(Work{id, s0});
-          }
+        ProbeSrc sr{};
+        sr.b = b;
+        sr.plane = plane;
+        sr.n = n;
+        sr.yoff = yoff[b];
+        sr.boff = boff[b];
+        sr.pstart = nvq;
+        sr.wstart = nwk;
+        const long long np = (long long)nc * plane;
+        nvq += np;
+        nwk += np * ((n + kBlock - 1) / kBlock);
+        src.push_back(sr);
+        reps.push_back(L.h[b]);
+        mult.push_back(np);
       }
-      if (vq.empty()) continue;
-      auto* dvq = (LInst*)upload(vq.data(), vq.size() * sizeof(LInst));
-      auto* dpc = (int*)upload(pc.data(), pc.size() * sizeof(int));
-      auto* dps = (int*)upload(ps.data(), ps.size() * sizeof(int));
-      auto* dbo = (long long*)upload(bo.data(), bo.size() * sizeof(long long));
-      auto* dwk = (Work*)upload(wk.data(), wk.size() * sizeof(Work));
-      launch_set_probe(st, dvq, dpc, dps, (int)vq.size(), ncolor, U);
+      if (src.empty()) continue;
+      if (nvq >= (1LL << 31) || nwk >= (1LL << 31)) throw std::string("too many coarsest-grid probes");
       // responses Y = S U of the probe vectors: one fused FP64 pass over the
-      // probe instances where the level's shape allows, else the two-pass
+      // probe instances where the level's shape allows (the tile geometry of
+      // each probed instance, repeated for its probes), else the two-pass
       // kernels
-      bool probed = false;
+      FTab ft;
+      std::vector<int2> torg;
+      long long ntile = 0;
+      bool fusedp = false;
       if constexpr (std::is_same<TC, float>::value) {
         if (P->opt.fused) {
-          FTab ft;
-          make_ftab(ft, vq, (int)vq.size(), std::vector<int>(vq.size(), 1), D, kFThreads64, sizeof(double));
+          make_ftab(ft, reps, (int)reps.size(), std::vector<int>(reps.size(), 1), D, kFThreads64, sizeof(double),
+                    &mult);
           if (ft.ok) {
-            auto* dt = (FTile*)upload(ft.h.data(), ft.h.size() * sizeof(FTile));
-            launch_apply3<double, double, float>(st, dt, ft.nb(), ft.g, dvq, P->ci, U, C(L.coef), G_STORE, Y,
-                                                 nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr);
-            probed = true;
+            std::vector<std::vector<int2>> org(reps.size());
+            for (const FTile& t : ft.h) org[t.inst].push_back(make_int2(t.x0, t.y0));
+            for (size_t k = 0; k < src.size(); ++k) {
+              src[k].tpp = (int)org[k].size();
+              src[k].toff = (int)torg.size();
+              src[k].tstart = ntile;
+              torg.insert(torg.end(), org[k].begin(), org[k].end());
+              ntile += mult[k] * src[k].tpp;
+            }
+            fusedp = ntile < (1LL << 31);
           }
         }
       }
-      if (!probed) {
-        launch_gamma<double, double, TC>(D, st, dwk, (int)wk.size(), dvq, P->ci, U, C(L.coef), C(P->f), 0, GM);
-        launch_gather<double, double, TC>(D, st, dwk, (int)wk.size(), dvq, P->ci, U, GM, C(L.coef), C(P->w), 0,
-                                          G_STORE, Y, nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr);
+      auto* dsrc = (ProbeSrc*)upload(src.data(), src.size() * sizeof(ProbeSrc));
+      auto* dorg = fusedp ? (int2*)upload(torg.data(), torg.size() * sizeof(int2)) : nullptr;
+      auto* dvq = (LInst*)scratch(nvq * sizeof(LInst));
+      auto* dpc = (int*)scratch(nvq * sizeof(int));
+      auto* dps = (int*)scratch(nvq * sizeof(int));
+      auto* dbo = (long long*)scratch(nvq * sizeof(long long));
+      auto* dwk = (Work*)scratch(nwk * sizeof(Work));
+      auto* dt = fusedp ? (FTile*)scratch(ntile * sizeof(FTile)) : nullptr;
+      launch_probe_lists(st, L.d, dsrc, (int)src.size(), nvq, nwk, ntile, dorg, dvq, dpc, dps, dbo, dwk, dt);
+      launch_set_probe(st, dvq, dpc, dps, (int)nvq, ncolor, U);
+      if (fusedp) {
+        if constexpr (std::is_same<TC, float>::value)
+          launch_apply3<double, double, float>(st, dt, (int)ntile, ft.g, dvq, P->ci, U, C(L.coef), G_STORE, Y,
+                                               nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr);
+      } else {
+        launch_gamma<double, double, TC>(D, st, dwk, (int)nwk, dvq, P->ci, U, C(L.coef), C(P->f), 0, GM);
+        launch_gather<double, double, TC>(D, st, dwk, (int)nwk, dvq, P->ci, U, GM, C(L.coef), C(P->w), 0, G_STORE, Y,
+                                          nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr);
       }
-      launch_extract_band(st, dwk, (int)wk.size(), dvq, dpc, dps, dbo, ncolor, Y, LB);
-      HIPCHK(hipStreamSynchronize(st));
+      launch_extract_band(st, dwk, (int)nwk, dvq, dpc, dps, dbo, ncolor, Y, LB);
     }
     auto* dboff = (long long*)upload(boff.data(), B * sizeof(long long));
     auto* dT = (int*)upload(Tn.data(), B * sizeof(int));

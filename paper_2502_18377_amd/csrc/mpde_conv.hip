@@ -336,6 +336,19 @@ __global__ void __launch_bounds__(256) k_energy_grad(const Work* __restrict__ wo
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// Per-instance norm and inverse norm from squared norms (0 for a zero or
+// non-finite norm), on the device so the learned correction needs no host
+// round trip.
+__global__ void k_norms(int B, const double* __restrict__ n2, double* __restrict__ norm,
+                        double* __restrict__ inv) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const double n = sqrt(fmax(n2[b], 0.0));
+  const bool ok = n > 0 && isfinite(n);
+  norm[b] = ok ? n : 0.0;
+  inv[b] = ok ? 1.0 / n : 0.0;
+}
+
 // Residual of the prolonged correction on the finer level of a coarse-grid
 // correction, w = S p - rhat with rhat = r / ||b|| (b the coarse right side).
 __global__ void __launch_bounds__(256) k_fine_resid(const Work* __restrict__ work, const LInst* __restrict__ li,
@@ -399,6 +412,10 @@ void energy_grad_launch(hipStream_t st, const Work* w, int nb, const LInst* li, 
   if (nb <= 0) return;
   hipLaunchKernelGGL(k_energy_grad, dim3(nb), dim3(256), 0, st, w, li, o, So, r, inv_norm, dinv, scale, dOut,
                      partial);
+}
+void norms_launch(hipStream_t st, int B, const double* n2, double* norm, double* inv) {
+  if (B <= 0) return;
+  hipLaunchKernelGGL(k_norms, dim3((B + 255) / 256), dim3(256), 0, st, B, n2, norm, inv);
 }
 void fine_resid_launch(hipStream_t st, const Work* w, int nb, const LInst* li, const float* Sp, const float* r,
                        const double* inv_norm, float* out) {

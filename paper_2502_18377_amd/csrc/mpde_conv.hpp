@@ -36,6 +36,9 @@ void predict_launch(hipStream_t st, const Work* w, int nb, const LInst* li, cons
 void energy_grad_launch(hipStream_t st, const Work* w, int nb, const LInst* li, const float* o, const float* So,
                         const float* r, const double* inv_norm, const float* dinv, float scale, float* dOut,
                         double* partial);
+// norm[b] = sqrt(n2[b]) and inv[b] = 1 / norm[b] (both 0 for a zero or
+// non-finite norm), B instances.
+void norms_launch(hipStream_t st, int B, const double* n2, double* norm, double* inv);
 // w = S p - r / ||b|| on the finer level of a coarse-grid correction.
 void fine_resid_launch(hipStream_t st, const Work* w, int nb, const LInst* li, const float* Sp, const float* r,
                        const double* inv_norm, float* out);

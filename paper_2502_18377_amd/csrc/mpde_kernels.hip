@@ -9,6 +9,7 @@
 // reduction in a fixed order (two-stage, no floating-point atomics).
 #include "mpde_internal.hpp"
 #include "mpde_kernels.hpp"
+#include "mpde_fused.hpp"
 
 namespace mpde {
 
@@ -670,6 +671,65 @@ constexpr int kBBMax = 64;
 
 __device__ __forceinline__ long long bb_at(long long base, int t, int k, int m) {
   return base + ((long long)t * 5 + k) * m * m;
+}
+
+// Probe instances of the coarsest-level probing, generated on the device.
+// Source k (a probed instance) owns probes pstart .. pstart + nc * plane - 1
+// in (colour c, plane point sp) order, c-major; each probe is a copy of the
+// instance's level descriptor whose vector offset points at its probe
+// vector (yoff + (c * plane + sp) * n).  Work items: ceil(n / kBlock) per
+// probe from wstart; fused-operator tiles: tpp per probe from tstart, with
+// origins torg[toff ..].  Sources are ordered, so the owner of an index is
+// found by binary search on the prefix starts.
+template <typename F>
+__device__ __forceinline__ int probe_owner(const ProbeSrc* src, int nsrc, long long i, F start) {
+  int lo = 0, hi = nsrc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start(src[mid]) <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+__global__ void __launch_bounds__(kBlock) k_probe_lists(const LInst* __restrict__ lc, const ProbeSrc* __restrict__ src,
+                                                        int nsrc, long long nvq, long long nwk, long long ntile,
+                                                        const int2* __restrict__ torg, LInst* __restrict__ vq,
+                                                        int* __restrict__ pc, int* __restrict__ ps,
+                                                        long long* __restrict__ bo, Work* __restrict__ wk,
+                                                        FTile* __restrict__ tiles) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (i < nvq) {
+    const ProbeSrc& S = src[probe_owner(src, nsrc, i, [](const ProbeSrc& x) { return x.pstart; })];
+    const long long loc = i - S.pstart;
+    const int c = (int)(loc / S.plane), sp = (int)(loc - (long long)c * S.plane);
+    LInst q = lc[S.b];
+    q.voff = S.yoff + ((long long)c * S.plane + sp) * S.n;
+    vq[i] = q;
+    pc[i] = c;
+    ps[i] = sp;
+    bo[i] = S.boff;
+  }
+  if (i < nwk) {
+    const ProbeSrc& S = src[probe_owner(src, nsrc, i, [](const ProbeSrc& x) { return x.wstart; })];
+    const long long loc = i - S.wstart;
+    const long long wpp = (S.n + kBlock - 1) / kBlock;
+    wk[i] = Work{(int)(S.pstart + loc / wpp), (int)(loc % wpp) * kBlock};
+  }
+  if (tiles && i < ntile) {
+    const ProbeSrc& S = src[probe_owner(src, nsrc, i, [](const ProbeSrc& x) { return x.tstart; })];
+    const long long loc = i - S.tstart;
+    const int2 o = torg[S.toff + (int)(loc % S.tpp)];
+    tiles[i] = FTile{(int)(S.pstart + loc / S.tpp), o.x, o.y, (int)i};
+  }
+}
+
+void launch_probe_lists(hipStream_t st, const LInst* lc, const ProbeSrc* src, int nsrc, long long nvq, long long nwk,
+                        long long ntile, const int2* torg, LInst* vq, int* pc, int* ps, long long* bo, Work* wk,
+                        FTile* tiles) {
+  const long long n = std::max(nvq, std::max(nwk, tiles ? ntile : 0LL));
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_probe_lists, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, lc, src, nsrc,
+                     nvq, nwk, ntile, torg, vq, pc, ps, bo, wk, tiles);
 }
 
 // Probe responses into the lower band blocks.

@@ -33,6 +33,21 @@ void launch_set_probe(hipStream_t st, const LInst* probe, const int* pc, const i
                       double* U);
 void launch_extract_probe(hipStream_t st, const Work* w, int nb, const LInst* probe, const int* pc, const int* ps,
                           const long long* dout, int ncolor, const double* Y, double* S);
+// One probed instance of the coarsest-level probing (see k_probe_lists).
+struct ProbeSrc {
+  int b;             // instance
+  int plane, n;      // points per time plane, points of its coarsest level
+  int tpp, toff;     // fused-operator tiles per probe and their origins in torg
+  long long yoff;    // first probe vector
+  long long boff;    // band storage
+  long long pstart, wstart, tstart;   // first probe, work item and tile index
+};
+struct FTile;
+// Probe descriptors, work items and (tiles != null) fused-operator tiles of
+// all probes, from nsrc sources and the coarsest-level descriptors lc.
+void launch_probe_lists(hipStream_t st, const LInst* lc, const ProbeSrc* src, int nsrc, long long nvq, long long nwk,
+                        long long ntile, const int2* torg, LInst* vq, int* pc, int* ps, long long* bo, Work* wk,
+                        FTile* tiles);
 void launch_extract_band(hipStream_t st, const Work* w, int nb, const LInst* probe, const int* pc, const int* ps,
                          const long long* bout, int ncolor, const double* Y, double* Lb);
 void launch_bb_factor(hipStream_t st, int nmat, double* Lb, const long long* boff, const int* T, const int* m,
