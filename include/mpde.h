@@ -97,7 +97,12 @@ typedef struct {
                             and y periodic, use the one-pass operator kernel
                             that evaluates every row once (1); zero: the
                             two-pass kernels (same operator, other rounding) */
-  int32_t reserved[4];
+  int32_t time_chunks;   /* one-pass operator: time chunks per tile, each
+                            with two halo row planes per side (same sums):
+                            0 = tiles and chunks chosen per launch from a
+                            cost model (default), 1 = whole time axis, 2 or
+                            4 = that many where the time axis allows */
+  int32_t reserved[3];
 } mpde_options;
 
 /* Problem description (the encoder outputs of Eq. 2 with uniform steps). */

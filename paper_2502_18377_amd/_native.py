@@ -25,7 +25,7 @@ class Options(ctypes.Structure):
                 ("nu", ctypes.c_int32), ("coarse_min", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("max_levels", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("out_f64", ctypes.c_int32), ("graph", ctypes.c_int32), ("fused", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("time_chunks", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class KStat(ctypes.Structure):

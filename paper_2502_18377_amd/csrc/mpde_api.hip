@@ -370,17 +370,18 @@ void make_table(Table& t, const std::vector<LInst>& h, int B, const std::vector<
 // tiles of its (x, y) plane; TX and TY are divisors of the largest extents,
 // common to the level, such that the rows of a tile plus halo fit one block
 // of `nth` threads (one row point each) and its staged u plane fits two
-// values per thread.  Among those, the level gets at least 512 blocks (two
-// per compute unit) where the shapes allow, and then the fewest wavefronts
-// in total: halo rows are evaluated by every tile that needs them, so this
-// minimises the redundant row work.  `esize` is the byte size of the
+// values per thread.  The tile shape and the number of time chunks (at most
+// `chunks`, 0 = up to 4) are those of least estimated time (below); halo
+// rows are evaluated by every tile that needs them and halo planes by every
+// chunk, so the estimate weighs that redundant work against the parallelism
+// it buys.  `esize` is the byte size of the
 // arithmetic type (LDS budget); `mult` (optional) counts each instance that
 // many times in the choice (instances that stand for several identical
 // ones).  Consecutive groups of 8 instances are
 // interleaved tile by tile, so that with round-robin block dispatch all
 // tiles of one instance (which share halos) run on the same XCD and its L2.
 void make_ftab(FTab& f, const std::vector<LInst>& h, int B, const std::vector<int>& sel, int D, int nth,
-               size_t esize, const std::vector<long long>* mult = nullptr) {
+               size_t esize, const std::vector<long long>* mult = nullptr, int chunks = 1) {
   f.h.clear();
   f.bstart.assign(B + 1, 0);
   f.ok = false;
@@ -432,27 +433,62 @@ void make_ftab(FTab& f, const std::vector<LInst>& h, int B, const std::vector<in
     if (mny % ty == 0)
       for (int tx = mnx; tx >= std::min(4, mnx); --tx)
         if (mnx % tx == 0) cand.push_back({tx, ty});
-  long long most = 0;
   std::vector<std::pair<std::pair<int, int>, Cut>> ok;
   for (auto& tt : cand) {
     Cut c;
     if (!cut(tt.first, tt.second, c)) continue;
     ok.push_back({tt, c});
-    most = std::max(most, c.tiles);
   }
   if (ok.empty()) return;
-  const long long want = std::min<long long>(512, most);
-  int bi = -1;
-  for (int i = 0; i < (int)ok.size(); ++i) {
-    if (ok[i].second.tiles < want) continue;
-    if (bi < 0 || ok[i].second.waves < ok[bi].second.waves) bi = i;
-  }
+  // time planes: common to every selected instance (nt > 0) or not (0)
+  int nt = -1, mnt = 0;
+  for (int b = 0; b < B; ++b)
+    if (sel[b] && h[b].N > 0) {
+      nt = (nt == -1 || nt == h[b].n[0]) ? h[b].n[0] : 0;
+      mnt = std::max(mnt, h[b].n[0]);
+    }
+  // time chunkings (count, planes per chunk): an even chunk length, so every
+  // chunk starts on an even plane, and chunk edges in [5, nt - 5]
+  std::vector<std::pair<int, int>> chk{{1, 0}};
+  if (nt > 0 && chunks != 1)
+    for (int want = 2; want <= (chunks == 0 ? 4 : chunks); want *= 2) {
+      const int tc = ((nt + want - 1) / want + 1) & ~1;
+      const int nc = (nt + tc - 1) / tc;
+      if (tc >= 5 && (nc - 1) * tc <= nt - 5 && nc > chk.back().first) chk.push_back({nc, tc});
+    }
+  if (chunks > 1) chk.erase(chk.begin(), chk.end() - 1);   // forced: the most chunks allowed
+  // Estimated launch time (us) of the FP32 one-pass kernel, a model fitted
+  // to its measured launches: a block's plane step takes at least 0.93 us
+  // (one wavefront per SIMD: the dependent chain of a step), and beyond that
+  // the 1024 SIMDs retire one wavefront plane step per 0.55 us each (issue
+  // bound).  The fewest wavefronts is not always the fastest choice: on
+  // small levels the latency term rules, and time chunks shorten it.
+  auto est = [&](const Cut& c, int nc, int tc) {
+    const int T = nt > 0 ? nt : mnt;
+    const double longest = nc == 1 ? T : nc == 2 ? std::max(tc + 2, T - tc + 2) : tc + 4;
+    const double total = (double)c.waves * (T + 4.0 * (nc - 1));
+    return std::max(0.93 * longest, 0.55 * total / 1024.0);
+  };
+  int bi = -1, bc = 0;
+  double best = 0;
+  for (int i = 0; i < (int)ok.size(); ++i)
+    for (int k = 0; k < (int)chk.size(); ++k) {
+      const double e = est(ok[i].second, chk[k].first, chk[k].second);
+      const long long w = ok[i].second.waves * chk[k].first;
+      if (bi < 0 || e < best - 1e-9 || (e <= best + 1e-9 && w < ok[bi].second.waves * chk[bc].first)) {
+        bi = i;
+        bc = k;
+        best = e;
+      }
+    }
   const int TX = ok[bi].first.first, TY = ok[bi].first.second;
   f.g.TX = TX;
   f.g.TY = TY;
   f.g.uplane = ok[bi].second.uplane;
   f.g.qplane = ok[bi].second.qplane;
   f.g.nthr = ok[bi].second.nthr;
+  f.g.nch = chk[bc].first;
+  f.g.tc = chk[bc].second;
   f.g.nt = -1;
   std::vector<std::vector<FTile>> per(B);
   int slot = 0;
@@ -1425,7 +1461,7 @@ int validate(const mpde_desc* d, mpde_options& opt) {
   }
   if (d->opts) opt = *d->opts; else mpde_default_options(&opt);
   if (!(opt.tol > 0) || opt.max_outer < 0 || opt.max_inner < 1 || opt.nu < 1 || opt.nu > 16 || opt.coarse_min < 4 ||
-      opt.max_levels < 1 || opt.inner_tol < 0 || opt.inner_tol >= 1)
+      opt.max_levels < 1 || opt.inner_tol < 0 || opt.inner_tol >= 1 || (opt.time_chunks != 0 && opt.time_chunks != 1 && opt.time_chunks != 2 && opt.time_chunks != 4))
     return fail(MPDE_ERR_INVALID_ARG, "invalid options");
   return MPDE_OK;
 }
@@ -1554,8 +1590,8 @@ void build_impl(mpde_problem* P, const mpde_desc* d) {
     make_table(L.all, L.h, B, sel_all);
     make_table(L.smooth, L.h, B, sel_smooth);
     make_table(L.dense, L.h, B, sel_dense);
-    make_ftab(L.fall, L.h, B, sel_all, D, kFThreads, sizeof(float));
-    make_ftab(L.fsmooth, L.h, B, sel_smooth, D, kFThreads, sizeof(float));
+    make_ftab(L.fall, L.h, B, sel_all, D, kFThreads, sizeof(float), nullptr, P->opt.time_chunks);
+    make_ftab(L.fsmooth, L.h, B, sel_smooth, D, kFThreads, sizeof(float), nullptr, P->opt.time_chunks);
     if (l == 0) make_ftab(L.fall64, L.h, B, sel_all, D, kFThreads64, sizeof(double));
   }
   // device structures

@@ -277,6 +277,18 @@ __global__ void __launch_bounds__(fthreads<TA>()) k_apply3(const FTile* __restri
   // trip count: the plane loop is unrolled completely and no prefetched
   // value is carried around a loop)
   const int nt = NT > 0 ? NT : L.n[0], nx = L.n[1], ny = L.n[2];
+  // Time chunks (gridDim.y > 1): block (tile, c) writes the output planes
+  // [t0, t1) and evaluates the rows of planes r0 .. (its last output) + 2.
+  // Away from the time boundary a row of plane r reaches the outputs
+  // r - 2 .. r + 2, and the rows of the first and last two planes reach five
+  // planes in, so chunk edges in [5, nt - 5] need two halo row planes on
+  // each side and nothing else (the host checks the edges; tc is even, so
+  // every chunk starts on an even plane).
+  // (the dot-product pass is never chunked: one partial-sum slot per tile)
+  const int nch = MODE == G_STORE_DOT ? 1 : (int)gridDim.y, ch = MODE == G_STORE_DOT ? 0 : (int)blockIdx.y;
+  const int t0 = ch * g.tc, t1 = ch == nch - 1 ? nt : t0 + g.tc;
+  const int r0 = ch == 0 ? 0 : t0 - 2;
+  const int tf = t1 < nt - 5 ? t1 : nt - 5;   // outputs below tf are finished in the plane loop
   const FSpan X = fspan(tl.x0, g.TX, nx, 1);
   const FSpan Y = fspan(tl.y0, g.TY, ny, 1);
   const int stt = L.str[0], stx = L.str[1], sty = L.str[2];   // an instance level has < 2^31 points
@@ -384,16 +396,17 @@ __global__ void __launch_bounds__(fthreads<TA>()) k_apply3(const FTile* __restri
 #pragma unroll
     for (int k = 0; k < kFMaxU; ++k) d[k] = bld<TV>(rU, uof[k], po);
   };
-  // planes 0..4 staged before the loop; plane p + 5 is staged at plane p
-  for (int pl = 0; pl < 5; ++pl) {
+  // planes r0 - 2 .. r0 + 4 staged before the loop; plane p + 5 is staged at
+  // plane p
+  for (int pl = r0 > 0 ? r0 - 2 : 0; pl < r0 + 5; ++pl) {
     const unsigned po = pvoff(pl);
 #pragma unroll
     for (int k = 0; k < kFMaxU; ++k) su[slot(pl) + uslot[k]] = bld<TV>(rU, uof[k], po);
   }
-  ld_coef(0, cs[0]);
-  ld_coef(1, cs[1]);
-  ld_u(5, us[0]);
-  ld_u(6, us[1]);
+  ld_coef(r0, cs[0]);
+  ld_coef(r0 + 1, cs[1]);
+  ld_u(r0 + 5, us[0]);
+  ld_u(r0 + 6, us[1]);
   __syncthreads();
 
   // Per-axis constants (uniform; FP32 copies made by the host): squared row
@@ -464,6 +477,10 @@ __global__ void __launch_bounds__(fthreads<TA>()) k_apply3(const FTile* __restri
     }
   };
   TV es[2][NQ][3];                   // epilogue inputs by plane parity
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int s = 0; s < NQ; ++s) es[q][s][0] = es[q][s][1] = es[q][s][2] = 0;
 
   // One plane.  Phase A evaluates the rows at plane p (staged u slot p & 1)
   // and stores the projected x and y rows in row buffer p & 1, then stages
@@ -473,7 +490,7 @@ __global__ void __launch_bounds__(fthreads<TA>()) k_apply3(const FTile* __restri
   // WP is the window position of plane p on the time axis (0, 1 on the
   // first two planes, 3, 4 on the last two, 2 elsewhere), a template
   // constant so that every ring index is fixed at compile time.
-  auto step = [&](int p, auto par, auto wpc) {
+  auto step = [&](int p, auto par, auto wpc) __attribute__((always_inline)) {
     constexpr int Q = decltype(par)::value;   // p & 1, also the ring offset
     constexpr int WP = decltype(wpc)::value;
     constexpr int tpt = WP != 4, tmt = WP != 0;
@@ -592,12 +609,13 @@ __global__ void __launch_bounds__(fthreads<TA>()) k_apply3(const FTile* __restri
         ra[4] += xy_gather<TA>(qx, qsl[s], Y.qs, Ax, B1dx, B2dx) + xy_gather<TA>(qy, qsl[s], 1, Ay, B1dy, B2dy);
       // plane p - 2 is complete unless it is one of the last five planes
       // (those are written after the last plane)
-      if (WP >= 2) finalize(p - 2, (p - 2 < nt - 5) ? gt[s] : kOOB, ra[2], su[slot(p - 2) + ad[s]], es[Q][s]);
+      if (WP >= 2)
+        finalize(p - 2, (p - 2 >= t0 && p - 2 < tf) ? gt[s] : kOOB, ra[2], su[slot(p - 2) + ad[s]], es[Q][s]);
       if (WP == 4) {   // p = nt - 1
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
           const int j = p - 4 + k;
-          if (j >= 0 && j >= nt - 5) {
+          if (j >= 0 && j >= nt - 5 && j >= t0) {
             TV e[3];
             ld_epi(j, gt[s], e);
             finalize(j, gt[s], ra[k], su[slot(j) + ad[s]], e);
@@ -619,21 +637,40 @@ __global__ void __launch_bounds__(fthreads<TA>()) k_apply3(const FTile* __restri
   using I2 = std::integral_constant<int, 2>;
   using I3 = std::integral_constant<int, 3>;
   using I4 = std::integral_constant<int, 4>;
-  step(0, I0(), I0());
-  step(1, I1(), I1());
-  int p = 2;
+  auto tail = [&](int p) __attribute__((always_inline)) {   // the last two planes, p = nt - 2
+    if (p & 1) {
+      step(p, I1(), I3());
+      step(p + 1, I0(), I4());
+    } else {
+      step(p, I0(), I3());
+      step(p + 1, I1(), I4());
+    }
+  };
+  if (nch == 1) {   // whole time axis (trip count fixed at compile time when NT > 0)
+    step(0, I0(), I0());
+    step(1, I1(), I1());
+    int p = 2;
 #pragma unroll
-  for (; p + 1 <= nt - 3; p += 2) {
-    step(p, I0(), I2());
-    step(p + 1, I1(), I2());
-  }
-  if (p <= nt - 3) step(p++, I0(), I2());
-  if (p & 1) {
-    step(p, I1(), I3());
-    step(p + 1, I0(), I4());
-  } else {
-    step(p, I0(), I3());
-    step(p + 1, I1(), I4());
+    for (; p + 1 <= nt - 3; p += 2) {
+      step(p, I0(), I2());
+      step(p + 1, I1(), I2());
+    }
+    if (p <= nt - 3) step(p++, I0(), I2());
+    tail(p);
+  } else {          // one chunk: interior planes in a loop unrolled by two
+    int p = r0;
+    if (ch == 0) {
+      step(0, I0(), I0());
+      step(1, I1(), I1());
+      p = 2;
+    }
+    const int pe = ch == nch - 1 ? nt - 3 : t1 + 1;
+    for (; p + 1 <= pe; p += 2) {
+      step(p, I0(), I2());
+      step(p + 1, I1(), I2());
+    }
+    if (p <= pe) step(p++, I0(), I2());
+    if (ch == nch - 1) tail(p);
   }
   if (MODE == G_STORE_DOT) {
     const double sdot = fblock_sum<NTH>((double)dot);
@@ -658,12 +695,15 @@ static void apply3_one(hipStream_t st, const FTile* tiles, int nb, FGeom g, cons
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)want);
     granted[dev] = want;
   }
+  // time chunks along y (not for the dot product: its per-tile partial sum
+  // has one slot per tile)
+  const dim3 grid((unsigned)nb, M == G_STORE_DOT || g.nch < 1 ? 1u : (unsigned)g.nch);
   if (e0 && e1)   // timed: the events take the dispatch's own start and end times
-    hipExtLaunchKernelGGL((k_apply3<TA, TV, TC, M, T, SIG>), dim3((unsigned)nb), dim3((unsigned)g.nthr), lds, st, e0,
-                          e1, 0, tiles, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial, f, w);
+    hipExtLaunchKernelGGL((k_apply3<TA, TV, TC, M, T, SIG>), grid, dim3((unsigned)g.nthr), lds, st, e0, e1, 0,
+                          tiles, g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial, f, w);
   else
-    hipLaunchKernelGGL((k_apply3<TA, TV, TC, M, T, SIG>), dim3((unsigned)nb), dim3((unsigned)g.nthr), lds, st, tiles,
-                       g, li, ci, u, c, out, bvec, x, r, d, dinv, cheb_step, partial, f, w);
+    hipLaunchKernelGGL((k_apply3<TA, TV, TC, M, T, SIG>), grid, dim3((unsigned)g.nthr), lds, st, tiles, g, li, ci,
+                       u, c, out, bvec, x, r, d, dinv, cheb_step, partial, f, w);
 }
 
 template <typename TA, typename TV, typename TC, int M>

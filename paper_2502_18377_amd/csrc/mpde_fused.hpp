@@ -28,6 +28,8 @@ struct FGeom {
   int nt;            // time planes of every instance of the launch, 0 if they differ
   int nthr;          // threads per block: the tiles' row points rounded up to whole
                      // wavefronts (at most fthreads<TA>(); staged u slots <= 2 nthr)
+  int nch;           // time chunks per tile (1: the whole time axis per block)
+  int tc;            // output planes per time chunk (even; chunk edges in [5, nt - 5])
 };
 
 // Ranges of one axis for a tile [x0, x0 + T) of an axis with n points:

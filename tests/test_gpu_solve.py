@@ -215,6 +215,35 @@ def test_fused_operator_mixed_batch():
         assert rel(z1[0], zf[k]) <= 1e-6
 
 
+@pytest.mark.parametrize("shape", [(32, 16, 16), (13, 16, 16), (30, 8, 16)])
+def test_time_chunks(shape):
+    # Splitting the time axis of the one-pass operator (4 chunks at 32 and
+    # 30 planes, the last one shorter at 30; 2 chunks at 13 with an odd last
+    # chunk; the forced split reaches every level of these batches).  Every
+    # output adds its rows in the same order, so where both launches run the
+    # same code (a run-time plane count: 13 and 30) six Krylov iterations
+    # after one FP64 residual agree bit for bit; at 32 planes the unsplit
+    # launch runs the fully unrolled variant, whose contractions into FMAs
+    # may differ, so they agree to FP32 rounding (a chunk that lost a halo
+    # row would change the preconditioner by far more).  Converged solves of
+    # both reach the oracle's normal equations.
+    insts = [as_dtype(W.reaction_diffusion_2d(i, shape=shape), "f32") for i in range(2)]
+    short = dict(tol=1e-14, inner_tol=1e-12, max_outer=1, max_inner=6, check_every=1, graph=0, out_f64=1)
+    _, a0, _ = gpu_solve(insts, "f32", time_chunks=1, **short)
+    _, a1, _ = gpu_solve(insts, "f32", time_chunks=4, **short)
+    for a, b in zip(a0, a1):
+        if shape[0] == 32:
+            assert rel(b, a) <= 1e-6
+        else:
+            assert np.array_equal(a, b)
+    _, z0, inf0 = gpu_solve(insts, "f32", tol=1e-9, out_f64=1, time_chunks=1)
+    _, z1, inf1 = gpu_solve(insts, "f32", tol=1e-9, out_f64=1, time_chunks=4)
+    assert all(s == 0 for s in inf1["status"]), inf1
+    for inst, a, b in zip(insts, z0, z1):
+        assert normal_relres(inst, b) <= 1e-9
+        assert rel(b, a) <= 1e-7
+
+
 def test_time_operator_modes():
     # mpde_time_operator: every pass times positive and reports the
     # algorithmic bytes of its mode (K = 6 coefficient planes, FP32 vectors;
