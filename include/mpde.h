@@ -75,8 +75,11 @@ enum { MPDE_STATUS_CONVERGED = 0, MPDE_STATUS_NOT_CONVERGED = 1, MPDE_STATUS_NON
 typedef struct {
   double tol;            /* target relative residual of the normal equations,
                             ||A^T(d - A z)|| / ||A^T d||, per instance (1e-6) */
-  double inner_tol;      /* relative reduction of each inner Krylov solve
-                            (F32: 1e-4, F64: 1e-10) */
+  double inner_tol;      /* relative reduction of each inner Krylov solve;
+                            0 (default): per instance and outer step, the
+                            reduction still needed (0.3 tol / relres),
+                            clamped to [max(1e-4, sqrt(0.3 tol)), 0.1] in
+                            F32 and [1e-10, 0.1] in F64 */
   int32_t max_outer;     /* outer refinement steps with an FP64 residual (30) */
   int32_t max_inner;     /* Krylov iterations per outer step (200) */
   int32_t nu;            /* smoothing steps before and after each coarse
@@ -277,7 +280,8 @@ int mpde_conv3d_wgrad(const void *x_bf16, const void *dy_bf16, float *dw, int32_
  * smoothing steps (nu), the inner Krylov tolerance and the number of Krylov
  * iterations per captured graph / host check, by coordinate search, and keep
  * the fastest in p's options.  chosen (host, may be NULL) receives
- * {nu, check_every, inner_tol * 1e9} of the winner; *best_ms its solve time.
+ * {nu, check_every, inner_tol * 1e9} of the winner (inner_tol 0: the
+ * adaptive default); *best_ms its solve time.
  * The solution state of p is overwritten (call mpde_solve afterwards). */
 int mpde_autotune(mpde_problem *p, void *z_scratch, int32_t *chosen, double *best_ms);
 

@@ -287,7 +287,8 @@ struct mpde_problem {
   void *e = nullptr, *rk = nullptr, *zk = nullptr, *pk = nullptr, *qk = nullptr;   // TV, level 0
   double* partial = nullptr;
   double *rz_new = nullptr, *rz = nullptr, *beta = nullptr, *pq = nullptr, *alpha = nullptr, *rn2 = nullptr,
-         *r0n2 = nullptr, *atd2 = nullptr, *scale = nullptr, *iscale = nullptr;
+         *r0n2 = nullptr, *atd2 = nullptr, *scale = nullptr, *iscale = nullptr,
+         *itol2 = nullptr;   // per-instance squared relative tolerance of the inner solve
   int *active = nullptr, *iters = nullptr, *flag = nullptr;
   void* Sinv = nullptr;                                    // TV dense inverses
   bool has_solution = false;
@@ -302,7 +303,6 @@ struct mpde_problem {
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   int gkey[2] = {0, 0};                                    // (nu, chunk) the graphs were captured with
   hipEvent_t gev[2] = {nullptr, nullptr};
-  double gtol = -1;
   void drop_graphs() {
     for (auto& g : gexec)
       if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
@@ -907,7 +907,8 @@ struct Solver {
   }
 
   // One PCG iteration (plain V-cycle preconditioner, no host interaction).
-  void pcg_iter(bool first, double tol2) {
+  void pcg_iter(bool first) {
+    const double* tol2 = P->itol2;
     Level& L0 = P->lv[0];
     const Table& t = L0.all;
     const int B = P->B;
@@ -927,15 +928,16 @@ struct Solver {
   }
 
   // Run `chunk` iterations through a captured graph (captured on first use
-  // for this (nu, chunk, tolerance) and replayed afterwards).
-  void pcg_chunk_graph(int which, int chunk, double tol2) {
+  // for this (nu, chunk) and replayed afterwards; the tolerances are read
+  // from the device).
+  void pcg_chunk_graph(int which, int chunk) {
     const int key = (P->opt.nu * 1000 + chunk) * 2 + which;
     if (!P->gst) {
       P->gst = stream_get();
       HIPCHK(hipEventCreateWithFlags(&P->gev[0], hipEventDisableTiming));
       HIPCHK(hipEventCreateWithFlags(&P->gev[1], hipEventDisableTiming));
     }
-    if (P->gexec[which] && (P->gkey[which] != key || P->gtol != tol2)) {
+    if (P->gexec[which] && P->gkey[which] != key) {
       (void)hipGraphExecDestroy(P->gexec[which]);
       P->gexec[which] = nullptr;
     }
@@ -945,7 +947,7 @@ struct Solver {
       hipStream_t keep = st;
       st = P->gst;
       HIPCHK(hipStreamBeginCapture(P->gst, hipStreamCaptureModeThreadLocal));
-      for (int k = 0; k < chunk; ++k) pcg_iter(which == 0 && k == 0, tol2);
+      for (int k = 0; k < chunk; ++k) pcg_iter(which == 0 && k == 0);
       hipGraph_t g = nullptr;
       hipError_t e = hipStreamEndCapture(P->gst, &g);
       st = keep;
@@ -954,7 +956,6 @@ struct Solver {
       (void)hipGraphDestroy(g);
       if (e != hipSuccess) throw HipError{e, "hipGraphInstantiate"};
       P->gkey[which] = key;
-      P->gtol = tol2;
     }
     HIPCHK(hipGraphLaunch(P->gexec[which], P->gst));
     HIPCHK(hipEventRecord(P->gev[1], P->gst));
@@ -962,7 +963,9 @@ struct Solver {
   }
 
   // PCG on S e = rk (level 0), e = 0 start; instances with active=0 stay frozen.
-  void pcg(double rel_tol, int max_it) {
+  // Inner Krylov solve: instance b stops once its residual fell by the
+  // factor whose square P->itol2[b] holds.
+  void pcg(int max_it) {
     Level& L0 = P->lv[0];
     const Table& t = L0.all;
     const int B = P->B;
@@ -972,12 +975,12 @@ struct Solver {
     if (P->net) launch_fill<TV>(st, t.d, t.nb(), L0.d, V(P->zp), 0.0);
     launch_dot<double, TV>(st, t.d, t.nb(), L0.d, V(P->rk), V(P->rk), P->partial);
     finish(t, P->r0n2);
-    const double tol2 = rel_tol * rel_tol;
+    const double* tol2 = P->itol2;
     std::vector<int> act(B);
     const int chunk = std::max(1, P->opt.check_every);
     if (P->opt.graph && !P->opt.profile && !P->net) {
       for (int it = 0; it < max_it; it += chunk) {
-        pcg_chunk_graph(it == 0 ? 0 : 1, chunk, tol2);
+        pcg_chunk_graph(it == 0 ? 0 : 1, chunk);
         HIPCHK(hipMemcpyAsync(act.data(), P->active, B * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         bool any = false;
@@ -1099,8 +1102,14 @@ struct Solver {
     HIPCHK(hipMemcpyAsync(nb.data(), norm2, B * sizeof(double), hipMemcpyDeviceToHost, st));
     launch_fill<double>(st, t.d, t.nb(), L0.d, u64, 0.0);
     HIPCHK(hipMemsetAsync(P->iters, 0, B * sizeof(int), st));
-    const double inner_tol = P->opt.inner_tol > 0 ? P->opt.inner_tol : (P->dtype == MPDE_F32 ? 1e-4 : 1e-10);
-    std::vector<double> relres(B, 1.0), sc(B), isc(B);
+    // Relative reduction asked of each inner solve: inner_tol if the caller
+    // set it; otherwise what instance b still needs, 0.3 tol / relres_b (a
+    // factor 3 of margin), at most 0.1 and at least a floor: in FP32 the
+    // larger of 1e-4 (what the FP32 recurrence resolves reliably) and
+    // sqrt(0.3 tol), so that two outer steps share the reduction instead
+    // of the first one overshooting it; in FP64 1e-10.
+    const double rho_min = P->dtype == MPDE_F32 ? std::max(1e-4, std::sqrt(0.3 * P->opt.tol)) : 1e-10;
+    std::vector<double> relres(B, 1.0), sc(B), isc(B), it2(B);
     std::vector<int> act(B);
     int code = MPDE_WARN_NOT_CONVERGED;
     for (int k = 0; k <= P->opt.max_outer; ++k) {
@@ -1118,14 +1127,21 @@ struct Solver {
         all &= !act[b];
         sc[b] = (rn[b] > 0 && std::isfinite(rn[b])) ? 1.0 / std::sqrt(rn[b]) : 0.0;
         isc[b] = (rn[b] > 0 && std::isfinite(rn[b])) ? std::sqrt(rn[b]) : 0.0;
+        double rho = P->opt.inner_tol;
+        if (!(rho > 0)) {
+          rho = relres[b] > 0 && std::isfinite(relres[b]) ? 0.3 * P->opt.tol / relres[b] : 0.1;
+          rho = std::min(0.1, std::max(rho_min, rho));
+        }
+        it2[b] = rho * rho;
       }
       if (all || k == P->opt.max_outer) { code = all ? MPDE_OK : MPDE_WARN_NOT_CONVERGED; break; }
       for (int b = 0; b < B; ++b) if (act[b]) outer[b] += 1;
       HIPCHK(hipMemcpyAsync(P->scale, sc.data(), B * sizeof(double), hipMemcpyHostToDevice, st));
       HIPCHK(hipMemcpyAsync(P->iscale, isc.data(), B * sizeof(double), hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(P->itol2, it2.data(), B * sizeof(double), hipMemcpyHostToDevice, st));
       HIPCHK(hipMemcpyAsync(P->active, act.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
       launch_copy_scale<double, TV>(st, t.d, t.nb(), L0.d, P->r64, V(P->rk), P->scale, 0);
-      pcg(inner_tol, P->opt.max_inner);
+      pcg(P->opt.max_inner);
       launch_copy_scale<TV, double>(st, t.d, t.nb(), L0.d, V(P->e), u64, P->iscale, 1);
     }
     HIPCHK(hipMemcpyAsync(itv.data(), P->iters, B * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1609,7 +1625,7 @@ void build_impl(mpde_problem* P, const mpde_desc* d) {
   const long long n0 = P->lv[0].npts;
   P->partial = P->alloc<double>(maxnb);
   for (double** a : {&P->rz_new, &P->rz, &P->beta, &P->pq, &P->alpha, &P->rn2, &P->r0n2, &P->atd2, &P->scale,
-                     &P->iscale, &P->rzp})
+                     &P->iscale, &P->rzp, &P->itol2})
     *a = P->alloc<double>(B);
   P->active = P->alloc<int>(B);
   P->iters = P->alloc<int>(B);
@@ -2005,7 +2021,7 @@ int mpde_autotune(mpde_problem* p, void* z, int32_t* chosen, double* best_ms) {
   if (chosen) {
     chosen[0] = cur.nu;
     chosen[1] = cur.check_every;
-    chosen[2] = (int32_t)std::lround((cur.inner_tol > 0 ? cur.inner_tol : (p->dtype == MPDE_F32 ? 1e-4 : 1e-10)) * 1e9);
+    chosen[2] = (int32_t)std::lround(cur.inner_tol * 1e9);   // 0: the adaptive default
   }
   if (best_ms) *best_ms = best;
   return MPDE_OK;

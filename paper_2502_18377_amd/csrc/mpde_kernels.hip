@@ -1167,8 +1167,8 @@ __global__ void __launch_bounds__(kBlock) k_finish_sum(const double* __restrict_
 // Scalar updates of PCG, one thread per instance.
 //   op 0: beta = active ? (first ? 0 : rz_new/rz) : 0; rz = rz_new
 //   op 1: alpha = active ? rz/pq : 0
-//   op 2: convergence test of rnorm2 against tol2*r0norm2; counts iterations
-__global__ void k_pcg_scalars(int op, int B, int first, double tol2, double* __restrict__ rz_new,
+//   op 2: convergence test of rnorm2 against tol2[b]*r0norm2; counts iterations
+__global__ void k_pcg_scalars(int op, int B, int first, const double* __restrict__ tol2, double* __restrict__ rz_new,
                               double* __restrict__ rz, double* __restrict__ beta, double* __restrict__ pq,
                               double* __restrict__ alpha, double* __restrict__ rn2, double* __restrict__ r0n2,
                               int* __restrict__ active, int* __restrict__ iters) {
@@ -1190,7 +1190,7 @@ __global__ void k_pcg_scalars(int op, int B, int first, double tol2, double* __r
     if (active[b]) {
       iters[b] += 1;
       const double r = rn2[b];
-      if (!(r > tol2 * r0n2[b])) active[b] = 0;   // converged or non-finite
+      if (!(r > tol2[b] * r0n2[b])) active[b] = 0;   // converged or non-finite
     }
   }
 }
@@ -1954,7 +1954,7 @@ void launch_finish_sum(hipStream_t st, const double* partial, const int* bstart,
   hipLaunchKernelGGL(k_finish_sum, dim3(B), dim3(kBlock), 0, st, partial, bstart, B, out);
 }
 
-void launch_pcg_scalars(hipStream_t st, int op, int B, int first, double tol2, double* rz_new, double* rz,
+void launch_pcg_scalars(hipStream_t st, int op, int B, int first, const double* tol2, double* rz_new, double* rz,
                         double* beta, double* pq, double* alpha, double* rn2, double* r0n2, int* active,
                         int* iters) {
   hipLaunchKernelGGL(k_pcg_scalars, dim3((B + 255) / 256), dim3(256), 0, st, op, B, first, tol2, rz_new, rz, beta,

@@ -72,7 +72,8 @@ void launch_dense_apply(hipStream_t st, const Work* w, int nb, const LInst* li, 
 template <typename TA, typename TV>
 void launch_dot(hipStream_t st, const Work* w, int nb, const LInst* li, const TV* a, const TV* b, double* partial);
 void launch_finish_sum(hipStream_t st, const double* partial, const int* bstart, int B, double* out);
-void launch_pcg_scalars(hipStream_t st, int op, int B, int first, double tol2, double* rz_new, double* rz,
+// (tol2: per-instance squared relative tolerance of the inner solve, device)
+void launch_pcg_scalars(hipStream_t st, int op, int B, int first, const double* tol2, double* rz_new, double* rz,
                         double* beta, double* pq, double* alpha, double* rn2, double* r0n2, int* active,
                         int* iters);
 // p = z + beta p, q = (r - rv) + beta q (= S p when rv = r - S z), and the
