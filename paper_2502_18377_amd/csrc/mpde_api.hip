@@ -345,11 +345,32 @@ struct mpde_problem {
 
 namespace {
 
-void upload_table(mpde_problem* P, Table& t) {
-  t.d = P->alloc<Work>(std::max<size_t>(t.h.size(), 1));
-  t.d_bstart = P->alloc<int>(t.bstart.size());
-  if (!t.h.empty()) HIPCHK(hipMemcpy(t.d, t.h.data(), t.h.size() * sizeof(Work), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(t.d_bstart, t.bstart.data(), t.bstart.size() * sizeof(int), hipMemcpyHostToDevice));
+// Host tables bound for one device arena: each add() reserves a 256-byte
+// aligned slot in a host image and remembers which device pointer to set;
+// commit() allocates the arena, copies the image in one transfer and sets
+// the pointers (one copy instead of a synchronous copy per table).
+struct Uploads {
+  std::vector<char> img;
+  std::vector<std::pair<void**, size_t>> slots;
+  template <typename T>
+  void add(T*& dst, const void* src, size_t bytes) {
+    const size_t off = (img.size() + 255) & ~size_t(255);
+    img.resize(off + std::max<size_t>(bytes, 1));
+    if (bytes) std::memcpy(img.data() + off, src, bytes);
+    slots.push_back({reinterpret_cast<void**>(&dst), off});
+  }
+  void commit(mpde_problem* P) {
+    char* a = P->alloc<char>(std::max<size_t>(img.size(), 1));
+    if (!img.empty()) HIPCHK(hipMemcpy(a, img.data(), img.size(), hipMemcpyHostToDevice));
+    for (auto& s : slots) *s.first = a + s.second;
+    img.clear();
+    slots.clear();
+  }
+};
+
+void upload_table(Uploads& U, Table& t) {
+  U.add(t.d, t.h.data(), t.h.size() * sizeof(Work));
+  U.add(t.d_bstart, t.bstart.data(), t.bstart.size() * sizeof(int));
 }
 
 // Work items over the points of the selected instances (instance-major).
@@ -513,12 +534,10 @@ void make_ftab(FTab& f, const std::vector<LInst>& h, int B, const std::vector<in
   f.ok = true;
 }
 
-void upload_ftab(mpde_problem* P, FTab& f) {
+void upload_ftab(Uploads& U, FTab& f) {
   if (!f.ok) return;
-  f.d = P->alloc<FTile>(f.h.size());
-  f.d_bstart = P->alloc<int>(f.bstart.size());
-  HIPCHK(hipMemcpy(f.d, f.h.data(), f.h.size() * sizeof(FTile), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(f.d_bstart, f.bstart.data(), f.bstart.size() * sizeof(int), hipMemcpyHostToDevice));
+  U.add(f.d, f.h.data(), f.h.size() * sizeof(FTile));
+  U.add(f.d_bstart, f.bstart.data(), f.bstart.size() * sizeof(int));
 }
 
 template <typename TV>
@@ -1610,13 +1629,13 @@ void build_impl(mpde_problem* P, const mpde_desc* d) {
     make_ftab(L.fsmooth, L.h, B, sel_smooth, D, kFThreads, sizeof(float), nullptr, P->opt.time_chunks);
     if (l == 0) make_ftab(L.fall64, L.h, B, sel_all, D, kFThreads64, sizeof(double));
   }
-  // device structures
+  // device structures (one arena, one copy)
   size_t maxnb = 1;
+  Uploads up;
   for (auto& L : P->lv) {
-    L.d = P->alloc<LInst>(B);
-    HIPCHK(hipMemcpy(L.d, L.h.data(), B * sizeof(LInst), hipMemcpyHostToDevice));
-    upload_table(P, L.all); upload_table(P, L.smooth); upload_table(P, L.dense);
-    upload_ftab(P, L.fall); upload_ftab(P, L.fsmooth); upload_ftab(P, L.fall64);
+    up.add(L.d, L.h.data(), B * sizeof(LInst));
+    upload_table(up, L.all); upload_table(up, L.smooth); upload_table(up, L.dense);
+    upload_ftab(up, L.fall); upload_ftab(up, L.fsmooth); upload_ftab(up, L.fall64);
     maxnb = std::max(maxnb, L.all.h.size());
     maxnb = std::max(maxnb, (size_t)L.fall.bstart.back());
     if (!L.fall64.bstart.empty()) maxnb = std::max(maxnb, (size_t)L.fall64.bstart.back());   // level 0 only
@@ -1639,8 +1658,8 @@ void build_impl(mpde_problem* P, const mpde_desc* d) {
   P->vloc = P->alloc<double>((size_t)2 * D * n0);
   P->zoff_h.resize(B);
   for (int b = 0; b < B; ++b) P->zoff_h[b] = (long long)P->V * P->lv[0].h[b].voff;
-  P->zoff = P->alloc<long long>(B);
-  HIPCHK(hipMemcpy(P->zoff, P->zoff_h.data(), B * sizeof(long long), hipMemcpyHostToDevice));
+  up.add(P->zoff, P->zoff_h.data(), B * sizeof(long long));
+  up.commit(P);
   // inputs (caller's device memory, same concatenated layout as level 0)
   HIPCHK(hipMemcpyAsync(P->lv[0].coef, d->coeff, (size_t)P->K * n0 * sizeof(TC), hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(P->f, d->rhs, n0 * sizeof(TC), hipMemcpyDeviceToDevice, st));
