@@ -762,22 +762,28 @@ __global__ void __launch_bounds__(kBlock) k_extract_band(const Work* __restrict_
 // updates B_ik -= L_ij L_kj^T) run as 64 x 64 x 64 products C = A B^T with
 // both operands staged transposed in LDS and a 4 x 4 register tile per
 // thread (256 threads cover the 64 x 64 result); blocks of a smaller plane
-// are zero-padded to 64.
+// are zero-padded to 64.  The block has two such groups of 256 threads,
+// which take two products of a plane at a time (they share the B operand:
+// L_jj^-T for the off-diagonal blocks, L_kj for the updates of column k).
 constexpr int kBBT = kBBMax + 4;   // staged operand stride (keeps 4-double groups 16-byte aligned)
+constexpr int kBBGroups = 2;
+constexpr int kBBThreads = kBBGroups * kBlock;
 
-// Stage the m x m row-major block G (global, or LDS when `lds_src`) into T
-// transposed and zero-padded: T[q][r] = G[r][q].
-__device__ __forceinline__ void bb_stage_t(double* __restrict__ T, const double* G, int m, int gstride) {
-  for (int e = threadIdx.x; e < kBBMax * kBBMax; e += kBlock) {
+// Stage the m x m row-major block G into T transposed and zero-padded,
+// T[q][r] = G[r][q], by the threads lt = 0 .. nth - 1 of the caller.
+__device__ __forceinline__ void bb_stage_t(double* __restrict__ T, const double* G, int m, int gstride, int lt,
+                                           int nth) {
+  for (int e = lt; e < kBBMax * kBBMax; e += nth) {
     const int r = e >> 6, q = e & 63;
     T[q * kBBT + r] = (r < m && q < m) ? G[r * gstride + q] : 0.0;
   }
 }
 
-// acc[a][b] = sum_q At[q][4tr + a] * Bt[q][4tc + b] for the thread's tile.
+// acc[a][b] = sum_q At[q][4tr + a] * Bt[q][4tc + b] for the tile of the
+// group's thread lt < 256.
 __device__ __forceinline__ void bb_tile_abt(const double* __restrict__ At, const double* __restrict__ Bt,
-                                            double (&acc)[4][4]) {
-  const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
+                                            double (&acc)[4][4], int lt) {
+  const int tr = lt >> 4, tc = lt & 15;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -796,28 +802,32 @@ __device__ __forceinline__ void bb_tile_abt(const double* __restrict__ At, const
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_bb_factor(double* __restrict__ Lb, const long long* __restrict__ boff,
+__global__ void __launch_bounds__(kBBThreads) k_bb_factor(double* __restrict__ Lb, const long long* __restrict__ boff,
                                                       const int* __restrict__ Tn, const int* __restrict__ mn,
                                                       int* __restrict__ fail) {
   const long long base = boff[blockIdx.x];
   const int T = Tn[blockIdx.x], m = mn[blockIdx.x];
   __shared__ double Ls[kBBMax][kBBMax + 1];            // Ls[k][r] = L[r][k], the factor's columns
   __shared__ double col[2][kBBMax], xr[2][kBBMax];     // broadcast pivot column / inverse row
-  __shared__ __align__(16) double S1[kBBMax * kBBT];   // staged A^T
-  __shared__ __align__(16) double S2[kBBMax * kBBT];   // staged B^T
+  __shared__ __align__(16) double S1[kBBGroups][kBBMax * kBBT];   // staged A^T, one per group
+  __shared__ __align__(16) double S2[kBBMax * kBBT];              // staged B^T, shared
   const int tid = threadIdx.x;
-  const int tr = tid >> 4, tc = tid & 15;
+  const int grp = tid / kBlock, lt = tid % kBlock;   // product group and thread within it
+  const int tr = lt >> 4, tc = lt & 15;
+  const bool g0 = grp == 0;                          // the diagonal factor runs on group 0
   // diagonal-block factor and inverse: thread (r, cb) keeps columns
   // c = cb + 4 i (i < 16) of row r in registers; a plane of m < 64 points
   // is padded with an identity block
-  const int r = tid >> 2, cb = tid & 3;
+  // (group 1 mirrors group 0's indices so that its reads stay in range;
+  // every write of the diagonal factor is group 0's)
+  const int r = lt >> 2, cb = lt & 3;
   for (int j = 0; j < T; ++j) {
     double* Bjj = Lb + bb_at(base, j, 0, m);
     double a[16], x[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int c = cb + 4 * i;
-      a[i] = (r < m && c < m) ? Bjj[r * m + c] : (r == c ? 1.0 : 0.0);
+      a[i] = (g0 && r < m && c < m) ? Bjj[r * m + c] : (r == c ? 1.0 : 0.0);
       x[i] = (r == c) ? 1.0 : 0.0;
     }
     // right-looking Cholesky, one barrier per pivot: the owners of column k
@@ -827,7 +837,7 @@ __global__ void __launch_bounds__(kBlock) k_bb_factor(double* __restrict__ Lb, c
 #pragma unroll
     for (int k = 0; k < kBBMax; ++k) {
       double* ck = col[k & 1];
-      if (cb == (k & 3)) ck[r] = a[k >> 2];
+      if (g0 && cb == (k & 3)) ck[r] = a[k >> 2];
       __syncthreads();
       double akk = ck[k];
       if (!(akk > 0)) {
@@ -836,8 +846,8 @@ __global__ void __launch_bounds__(kBlock) k_bb_factor(double* __restrict__ Lb, c
       }
       const double piv = sqrt(akk), rinv = 1.0 / akk;
       const double ark = ck[r];
-      if (cb == (k & 3)) Ls[k][r] = r >= k ? (r == k ? piv : ark / piv) : 0.0;
-      if (r > k) {
+      if (g0 && cb == (k & 3)) Ls[k][r] = r >= k ? (r == k ? piv : ark / piv) : 0.0;
+      if (g0 && r > k) {
         const double f = ark * rinv;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
@@ -852,7 +862,7 @@ __global__ void __launch_bounds__(kBlock) k_bb_factor(double* __restrict__ Lb, c
     for (int k = 0; k < kBBMax; ++k) {
       double* xk = xr[k & 1];
       const double dk = 1.0 / Ls[k][k];
-      if (r == k) {
+      if (g0 && r == k) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           x[i] *= dk;
@@ -860,7 +870,7 @@ __global__ void __launch_bounds__(kBlock) k_bb_factor(double* __restrict__ Lb, c
         }
       }
       __syncthreads();
-      if (r > k) {
+      if (g0 && r > k) {
         const double lrk = Ls[k][r];
 #pragma unroll
         for (int i = 0; i < 16; ++i)
@@ -870,48 +880,58 @@ __global__ void __launch_bounds__(kBlock) k_bb_factor(double* __restrict__ Lb, c
     // Linv row-major into the diagonal block (k_bb_solve* read the inverse
     // there), and transposed into S2 (S2[c][r] = Linv[r][c]), the staged B^T
     // of the products B_ij Linv^T below
+    if (g0) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int c = cb + 4 * i;
-      if (r < m && c < m) Bjj[r * m + c] = x[i];
-      S2[c * kBBT + r] = x[i];
+      for (int i = 0; i < 16; ++i) {
+        const int c = cb + 4 * i;
+        if (r < m && c < m) Bjj[r * m + c] = x[i];
+        S2[c * kBBT + r] = x[i];
+      }
     }
     // B^T operand of L_ij = B_ij Linv^T is Linv^T[q][c] = Linv[c][q] = S2[q][c]: in place.
     __syncthreads();
     const int ie = min(T - 1, j + 4);
-    for (int i = j + 1; i <= ie; ++i) {
-      double* Bij = Lb + bb_at(base, i, i - j, m);
-      bb_stage_t(S1, Bij, m, m);
+    // off-diagonal blocks, two at a time (group g takes block i0 + g)
+    for (int i0 = j + 1; i0 <= ie; i0 += kBBGroups) {
+      const int i = i0 + grp;
+      double* Bij = Lb + bb_at(base, min(i, ie), min(i, ie) - j, m);
+      if (i <= ie) bb_stage_t(S1[grp], Bij, m, m, lt, kBlock);
       __syncthreads();
-      double acc[4][4];
-      bb_tile_abt(S1, S2, acc);
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int r = 4 * tr + a, cc = 4 * tc + b;
-          if (r < m && cc < m) Bij[r * m + cc] = acc[a][b];
-        }
-      __syncthreads();
-    }
-    // trailing update: B_ik -= L_ij L_kj^T for j < k <= i <= j + 4
-    for (int k = j + 1; k <= ie; ++k) {
-      const double* Lkj = Lb + bb_at(base, k, k - j, m);
-      bb_stage_t(S2, Lkj, m, m);
-      for (int i = k; i <= ie; ++i) {
-        const double* Lij = Lb + bb_at(base, i, i - j, m);
-        bb_stage_t(S1, Lij, m, m);
-        __syncthreads();
+      if (i <= ie) {
         double acc[4][4];
-        bb_tile_abt(S1, S2, acc);
-        double* Bik = Lb + bb_at(base, i, i - k, m);
+        bb_tile_abt(S1[grp], S2, acc, lt);
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
           for (int b = 0; b < 4; ++b) {
             const int r = 4 * tr + a, cc = 4 * tc + b;
-            if (r < m && cc < m) Bik[r * m + cc] -= acc[a][b];
+            if (r < m && cc < m) Bij[r * m + cc] = acc[a][b];
           }
+      }
+      __syncthreads();
+    }
+    // trailing update: B_ik -= L_ij L_kj^T for j < k <= i <= j + 4, the
+    // blocks i of one column k two at a time
+    for (int k = j + 1; k <= ie; ++k) {
+      const double* Lkj = Lb + bb_at(base, k, k - j, m);
+      bb_stage_t(S2, Lkj, m, m, tid, kBBThreads);
+      for (int i0 = k; i0 <= ie; i0 += kBBGroups) {
+        const int i = i0 + grp;
+        const double* Lij = Lb + bb_at(base, min(i, ie), min(i, ie) - j, m);
+        if (i <= ie) bb_stage_t(S1[grp], Lij, m, m, lt, kBlock);
+        __syncthreads();
+        if (i <= ie) {
+          double acc[4][4];
+          bb_tile_abt(S1[grp], S2, acc, lt);
+          double* Bik = Lb + bb_at(base, i, i - k, m);
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+              const int r = 4 * tr + a, cc = 4 * tc + b;
+              if (r < m && cc < m) Bik[r * m + cc] -= acc[a][b];
+            }
+        }
         __syncthreads();
       }
     }
@@ -1625,7 +1645,7 @@ void launch_extract_band(hipStream_t st, const Work* w, int nb, const LInst* pro
 void launch_bb_factor(hipStream_t st, int nmat, double* Lb, const long long* boff, const int* T, const int* m,
                       int* fail) {
   if (nmat <= 0) return;
-  hipLaunchKernelGGL(k_bb_factor, dim3(nmat), dim3(kBlock), 0, st, Lb, boff, T, m, fail);
+  hipLaunchKernelGGL(k_bb_factor, dim3(nmat), dim3(kBBThreads), 0, st, Lb, boff, T, m, fail);
 }
 
 // Specialisation for 64-point planes: thread (r, h) owns 16 consecutive
