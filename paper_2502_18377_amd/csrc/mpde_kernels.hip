@@ -1159,16 +1159,24 @@ __global__ void __launch_bounds__(kBlock) k_dense_apply(const Work* __restrict__
 }
 
 // ---------------------------------------------------------------- Krylov
+// Per-work-item partial sums of a.b: one wavefront per work item of kBlock
+// points, each lane summing kBlock / 64 points in a fixed order, then a
+// fixed cross-lane tree (no LDS, no barrier).
+constexpr int kDotLanes = 64;
 template <typename TA, typename TV>
-__global__ void __launch_bounds__(kBlock) k_dot(const Work* __restrict__ work, const LInst* __restrict__ li,
-                                                const TV* __restrict__ a, const TV* __restrict__ b,
-                                                double* __restrict__ partial) {
+__global__ void __launch_bounds__(kDotLanes) k_dot(const Work* __restrict__ work, const LInst* __restrict__ li,
+                                                   const TV* __restrict__ a, const TV* __restrict__ b,
+                                                   double* __restrict__ partial) {
   const Work wk = work[blockIdx.x];
   const LInst& L = li[wk.inst];
-  const int j = wk.start + threadIdx.x;
   double v = 0;
-  if (j < L.N) v = (double)a[L.voff + j] * (double)b[L.voff + j];
-  v = block_sum(v);
+#pragma unroll
+  for (int i = 0; i < kBlock / kDotLanes; ++i) {
+    const int j = wk.start + threadIdx.x + kDotLanes * i;
+    if (j < L.N) v = fma((double)a[L.voff + j], (double)b[L.voff + j], v);
+  }
+#pragma unroll
+  for (int off = kDotLanes / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kDotLanes);
   if (threadIdx.x == 0) partial[blockIdx.x] = v;
 }
 
@@ -1967,7 +1975,7 @@ void launch_dense_apply(hipStream_t st, const Work* w, int nb, const LInst* li, 
 template <typename TA, typename TV>
 void launch_dot(hipStream_t st, const Work* w, int nb, const LInst* li, const TV* a, const TV* b, double* partial) {
   if (nb <= 0) return;
-  hipLaunchKernelGGL((k_dot<TA, TV>), GRID(nb), w, li, a, b, partial);
+  hipLaunchKernelGGL((k_dot<TA, TV>), dim3((unsigned)nb), dim3(kDotLanes), 0, st, w, li, a, b, partial);
 }
 
 void launch_finish_sum(hipStream_t st, const double* partial, const int* bstart, int B, double* out) {
