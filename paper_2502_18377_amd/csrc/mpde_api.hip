@@ -226,6 +226,8 @@ struct FTab {
 struct Level {
   std::vector<LInst> h;        // [B]; N = 0 for instances without this level
   LInst* d = nullptr;
+  std::vector<LInst> hg;       // h with the Krylov gate (act) set, and its device copy
+  LInst* dg = nullptr;
   long long npts = 0;          // total points of this level
   Table all, smooth, dense;    // all instances / non-coarsest / coarsest (rows)
   FTab fall, fsmooth;          // fused-operator tiles for `all` and `smooth`
@@ -367,6 +369,14 @@ struct Uploads {
     slots.clear();
   }
 };
+
+// The gated copy of a level's descriptors: act points at the instance's
+// active flag, so that the kernels of a Krylov iteration skip converged
+// instances.
+void gate_copy(mpde_problem* P, Level& L) {
+  L.hg = L.h;
+  for (size_t b = 0; b < L.hg.size(); ++b) L.hg[b].act = P->active + b;
+}
 
 void upload_table(Uploads& U, Table& t) {
   U.add(t.d, t.h.data(), t.h.size() * sizeof(Work));
@@ -723,6 +733,9 @@ struct Solver {
   TC* C(void* p) { return (TC*)p; }
 
   void finish(const Table& t, double* out) { launch_finish_sum(st, P->partial, t.d_bstart, P->B, out); }
+  // Descriptors to launch with: the gated copy inside the Krylov iterations.
+  bool gate = false;
+  const LInst* LD(const Level& L) const { return gate ? L.dg : L.d; }
 
   // Profiling of finest-grid kernels: kind 0 = gamma, 1 = gather, 2 = fused
   // three-axis operator.  Bytes are
@@ -795,17 +808,17 @@ struct Solver {
       if constexpr (std::is_same<TV, float>::value && std::is_same<TC, float>::value) {
         // timed launches carry their events in the dispatch itself
         hipEvent_t e0 = prof(l) ? P->ev() : nullptr, e1 = prof(l) ? P->ev() : nullptr;
-        launch_apply3<float, float, float>(st, f->d, f->nb(), f->g, L.d, P->ci, u, C(L.coef), mode, out, b, x, r, d,
+        launch_apply3<float, float, float>(st, f->d, f->nb(), f->g, LD(L), P->ci, u, C(L.coef), mode, out, b, x, r, d,
                                            V(L.dinv), cheb_step, partial, e0, e1);
         if (e0 && e1) precord(2, e0, e1, t, mode);
       }
       return;
     }
     pbeg(l);
-    launch_gamma<TV, TV, TC>(D, st, t.d, t.nb(), L.d, P->ci, u, C(L.coef), C(P->f), 0, V(L.gam));
+    launch_gamma<TV, TV, TC>(D, st, t.d, t.nb(), LD(L), P->ci, u, C(L.coef), C(P->f), 0, V(L.gam));
     pend(l, 0, t, 0);
     pbeg(l);
-    launch_gather<TV, TV, TC>(D, st, t.d, t.nb(), L.d, P->ci, u, V(L.gam), C(L.coef), C(P->w), 0, mode, out, b, x,
+    launch_gather<TV, TV, TC>(D, st, t.d, t.nb(), LD(L), P->ci, u, V(L.gam), C(L.coef), C(P->w), 0, mode, out, b, x,
                               r, d, V(L.dinv), cheb_step, partial);
     pend(l, 1, t, mode);
   }
@@ -893,20 +906,20 @@ struct Solver {
     Level& L = P->lv[l];
     const int nu = P->opt.nu;
     if (!L.cinst64.empty())
-      launch_bb_solve64<TV>(st, (int)L.cinst64.size(), L.d_cinst64, L.d, V(P->Sinv), b, x);
+      launch_bb_solve64<TV>(st, (int)L.cinst64.size(), L.d_cinst64, LD(L), V(P->Sinv), b, x);
     if (!L.cinst16.empty())
-      launch_bb_solve16<TV>(st, (int)L.cinst16.size(), L.d_cinst16, L.d, V(P->Sinv), b, x);
-    if (!L.cinstg.empty()) launch_bb_solve<TV>(st, (int)L.cinstg.size(), L.d_cinstg, L.d, V(P->Sinv), b, x);
+      launch_bb_solve16<TV>(st, (int)L.cinst16.size(), L.d_cinst16, LD(L), V(P->Sinv), b, x);
+    if (!L.cinstg.empty()) launch_bb_solve<TV>(st, (int)L.cinstg.size(), L.d_cinstg, LD(L), V(P->Sinv), b, x);
     if (L.smooth.nb() == 0) return;
     const Table& t = L.smooth;
-    if (!started) launch_cheb_init<TV>(st, t.d, t.nb(), L.d, b, V(L.dinv), x, V(L.r), V(L.dd));
+    if (!started) launch_cheb_init<TV>(st, t.d, t.nb(), LD(L), b, V(L.dinv), x, V(L.r), V(L.dd));
     chebyshev(l, x, nu);
     Level& Cc = P->lv[l + 1];
-    launch_restrict<TV>(D, st, Cc.all.d, Cc.all.nb(), L.d, Cc.d, V(L.r), V(Cc.b), V(Cc.dinv), V(Cc.x), V(Cc.r),
+    launch_restrict<TV>(D, st, Cc.all.d, Cc.all.nb(), LD(L), LD(Cc), V(L.r), V(Cc.b), V(Cc.dinv), V(Cc.x), V(Cc.r),
                         V(Cc.dd));
     if (use_net && P->net && l + 1 == P->net_level) learned(l + 1, V(Cc.b), V(Cc.x));
     else vcycle(l + 1, V(Cc.b), V(Cc.x), true);
-    launch_prolong_add<TV>(D, st, t.d, t.nb(), L.d, Cc.d, V(Cc.x), x);
+    launch_prolong_add<TV>(D, st, t.d, t.nb(), LD(L), LD(Cc), V(Cc.x), x);
     op(l, t, x, G_RESID, V(L.r), b, nullptr, nullptr, V(L.dd), 0, nullptr);
     chebyshev(l, x, nu);
   }
@@ -920,7 +933,7 @@ struct Solver {
     Level& L0 = P->lv[0];
     const Table& t = L0.all;
     if (L0.dense.nb() > 0) launch_fill<TV>(st, L0.dense.d, L0.dense.nb(), L0.d, V(L0.r), (TV)0);
-    launch_update_pq<TV>(st, t.d, t.nb(), L0.d, P->beta, V(P->zk), V(P->rk), V(L0.r), V(P->pk), V(P->qk),
+    launch_update_pq<TV>(st, t.d, t.nb(), LD(L0), P->beta, V(P->zk), V(P->rk), V(L0.r), V(P->pk), V(P->qk),
                          P->partial);
     finish(t, P->pq);
   }
@@ -932,14 +945,14 @@ struct Solver {
     const Table& t = L0.all;
     const int B = P->B;
     vcycle(0, V(P->rk), V(P->zk), !first);   // after the first iteration update_xr wrote the start
-    launch_dot<double, TV>(st, t.d, t.nb(), L0.d, V(P->rk), V(P->zk), P->partial);
+    launch_dot<double, TV>(st, t.d, t.nb(), LD(L0), V(P->rk), V(P->zk), P->partial);
     finish(t, P->rz_new);
     launch_pcg_scalars(st, 0, B, first, tol2, P->rz_new, P->rz, P->beta, P->pq, P->alpha, P->rn2, P->r0n2,
                        P->active, P->iters);
     update_pq();
     launch_pcg_scalars(st, 1, B, 0, tol2, P->rz_new, P->rz, P->beta, P->pq, P->alpha, P->rn2, P->r0n2, P->active,
                        P->iters);
-    launch_update_xr<TV>(st, t.d, t.nb(), L0.d, P->alpha, V(P->pk), V(P->qk), V(P->e), V(P->rk), P->partial,
+    launch_update_xr<TV>(st, t.d, t.nb(), LD(L0), P->alpha, V(P->pk), V(P->qk), V(P->e), V(P->rk), P->partial,
                          V(L0.dinv), V(P->zk), V(L0.r), V(L0.dd));
     finish(t, P->rn2);
     launch_pcg_scalars(st, 2, B, 0, tol2, P->rz_new, P->rz, P->beta, P->pq, P->alpha, P->rn2, P->r0n2, P->active,
@@ -994,6 +1007,13 @@ struct Solver {
     if (P->net) launch_fill<TV>(st, t.d, t.nb(), L0.d, V(P->zp), 0.0);
     launch_dot<double, TV>(st, t.d, t.nb(), L0.d, V(P->rk), V(P->rk), P->partial);
     finish(t, P->r0n2);
+    // the iterations (and the graphs captured from them) launch with the
+    // gated descriptors: instances that have converged are skipped
+    struct GateOn {
+      bool& g;
+      explicit GateOn(bool& x) : g(x) { g = true; }
+      ~GateOn() { g = false; }
+    } gate_on(gate);
     const double* tol2 = P->itol2;
     std::vector<int> act(B);
     const int chunk = std::max(1, P->opt.check_every);
@@ -1016,7 +1036,7 @@ struct Solver {
     for (int it = 0; it < max_it; ++it) {
       use_net = use_net_solve;
       vcycle(0, V(P->rk), V(P->zk), it > 0);   // after the first iteration update_xr wrote the start
-      launch_dot<double, TV>(st, t.d, t.nb(), L0.d, V(P->rk), V(P->zk), P->partial);
+      launch_dot<double, TV>(st, t.d, t.nb(), LD(L0), V(P->rk), V(P->zk), P->partial);
       finish(t, P->rz_new);
       if (flex) {
         // Guard: a learned correction that is not a descent direction for
@@ -1046,7 +1066,7 @@ struct Solver {
       update_pq();
       launch_pcg_scalars(st, 1, B, 0, tol2, P->rz_new, P->rz, P->beta, P->pq, P->alpha, P->rn2, P->r0n2, P->active,
                          P->iters);
-      launch_update_xr<TV>(st, t.d, t.nb(), L0.d, P->alpha, V(P->pk), V(P->qk), V(P->e), V(P->rk), P->partial,
+      launch_update_xr<TV>(st, t.d, t.nb(), LD(L0), P->alpha, V(P->pk), V(P->qk), V(P->e), V(P->rk), P->partial,
                          V(L0.dinv), V(P->zk), V(L0.r), V(L0.dd));
       finish(t, P->rn2);
       launch_pcg_scalars(st, 2, B, 0, tol2, P->rz_new, P->rz, P->beta, P->pq, P->alpha, P->rn2, P->r0n2, P->active,
@@ -1215,6 +1235,8 @@ struct Solver {
         L.h[b].cheb_delta = 0.5 * (hi - lo);
       }
       HIPCHK(hipMemcpyAsync(L.d, L.h.data(), L.h.size() * sizeof(LInst), hipMemcpyHostToDevice, st));
+      gate_copy(P, L);
+      HIPCHK(hipMemcpyAsync(L.dg, L.hg.data(), L.hg.size() * sizeof(LInst), hipMemcpyHostToDevice, st));
     }
   }
 
@@ -1385,8 +1407,11 @@ struct Solver {
           L.h[b].doff = boff[b];
           (mn[b] == 64 ? L.cinst64 : mn[b] <= 16 ? L.cinst16 : L.cinstg).push_back(b);
         }
-      if (!L.cinst64.empty() || !L.cinst16.empty() || !L.cinstg.empty())
+      if (!L.cinst64.empty() || !L.cinst16.empty() || !L.cinstg.empty()) {
         HIPCHK(hipMemcpyAsync(L.d, L.h.data(), L.h.size() * sizeof(LInst), hipMemcpyHostToDevice, st));
+        gate_copy(P, L);
+        HIPCHK(hipMemcpyAsync(L.dg, L.hg.data(), L.hg.size() * sizeof(LInst), hipMemcpyHostToDevice, st));
+      }
       if (!L.cinst16.empty()) {
         L.d_cinst16 = P->alloc<int>(L.cinst16.size());
         HIPCHK(hipMemcpyAsync(L.d_cinst16, L.cinst16.data(), L.cinst16.size() * sizeof(int), hipMemcpyHostToDevice, st));
@@ -1632,8 +1657,11 @@ void build_impl(mpde_problem* P, const mpde_desc* d) {
   // device structures (one arena, one copy)
   size_t maxnb = 1;
   Uploads up;
+  P->active = P->alloc<int>(B);
   for (auto& L : P->lv) {
     up.add(L.d, L.h.data(), B * sizeof(LInst));
+    gate_copy(P, L);
+    up.add(L.dg, L.hg.data(), B * sizeof(LInst));
     upload_table(up, L.all); upload_table(up, L.smooth); upload_table(up, L.dense);
     upload_ftab(up, L.fall); upload_ftab(up, L.fsmooth); upload_ftab(up, L.fall64);
     maxnb = std::max(maxnb, L.all.h.size());
@@ -1646,7 +1674,6 @@ void build_impl(mpde_problem* P, const mpde_desc* d) {
   for (double** a : {&P->rz_new, &P->rz, &P->beta, &P->pq, &P->alpha, &P->rn2, &P->r0n2, &P->atd2, &P->scale,
                      &P->iscale, &P->rzp, &P->itol2})
     *a = P->alloc<double>(B);
-  P->active = P->alloc<int>(B);
   P->iters = P->alloc<int>(B);
   P->flag = P->alloc<int>(1);
   P->u64 = P->alloc<double>(n0);

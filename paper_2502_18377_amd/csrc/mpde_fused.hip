@@ -273,6 +273,7 @@ __global__ void __launch_bounds__(fthreads<TA>()) k_apply3(const FTile* __restri
   S4* sq = reinterpret_cast<S4*>(su + kFRing * g.uplane);   // [2][2][qplane] projected x, y rows
   const FTile tl = tiles[blockIdx.x];
   const LInst& L = li[tl.inst];
+  if (gated_off(L)) return;   // converged instance (Krylov iterations only)
   // NT > 0: every instance of the launch has NT time planes (a compile-time
   // trip count: the plane loop is unrolled completely and no prefetched
   // value is carried around a loop)

@@ -55,11 +55,17 @@ struct LInst {
   long long voff;      // offset (points) of this instance in level vectors
   long long coff;      // offset (elements) of its coefficient block (K planes)
   long long doff;      // offset (elements) of its dense coarsest inverse
+  // Krylov gate: the instance's active flag in the copy of the level's
+  // descriptors that the Krylov iterations launch with (kernels of an
+  // iteration return at once for a converged instance); null elsewhere.
+  const int* act;
   // FP32 copies of per-axis constants for the fused operator (FK_* indices):
   // wT^2, wT^2 / 2, wC1^2, wC2^2, 1/s, 1/s^2, the Gram inverses and
   // wC1^2 / 12, wC2^2 / 12.
   float fk[kMaxD][16];
 };
+
+__host__ __device__ inline bool gated_off(const LInst& L) { return L.act != nullptr && *L.act == 0; }
 
 // Indices into LInst::fk.  Class 0 (both Taylor rows) has a diagonal Gram
 // block, so only its two diagonal entries are kept.

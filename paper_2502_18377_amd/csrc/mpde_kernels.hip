@@ -203,6 +203,7 @@ __global__ void __launch_bounds__(kBlock) k_gamma(const Work* __restrict__ work,
                                                   const TC* __restrict__ f, int sigma, TV* __restrict__ gam) {
   const Work w = work[blockIdx.x];
   const LInst& L = li[w.inst];
+  if (gated_off(L)) return;   // converged instance (Krylov iterations only)
   const int p = w.start + threadIdx.x;
   if (p >= L.N) return;
   int ic[kMaxD];
@@ -222,6 +223,7 @@ __global__ void __launch_bounds__(kBlock) k_gather(const Work* __restrict__ work
                                                    double* __restrict__ partial) {
   const Work wk = work[blockIdx.x];
   const LInst& L = li[wk.inst];
+  if (gated_off(L)) return;   // converged instance (Krylov iterations only)
   const int j = wk.start + threadIdx.x;
   const bool live = j < L.N;
   TA y = 0, uj = 0;
@@ -436,6 +438,7 @@ __global__ void __launch_bounds__(kBlock) k_cheb_init(const Work* __restrict__ w
                                                       TV* __restrict__ x, TV* __restrict__ r, TV* __restrict__ d) {
   const Work wk = work[blockIdx.x];
   const LInst& L = li[wk.inst];
+  if (gated_off(L)) return;   // converged instance (Krylov iterations only)
   const int j = wk.start + threadIdx.x;
   if (j >= L.N) return;
   const long long g = L.voff + j;
@@ -511,6 +514,7 @@ __global__ void __launch_bounds__(kBlock) k_restrict(const Work* __restrict__ wo
   const Work wk = work[blockIdx.x];
   const LInst& C = lc[wk.inst];
   const LInst& F = lf[wk.inst];
+  if (gated_off(C)) return;   // converged instance (Krylov iterations only)
   const int jc = wk.start + threadIdx.x;
   if (jc >= C.N) return;
   int cc[kMaxD];
@@ -550,6 +554,7 @@ __global__ void __launch_bounds__(kBlock) k_prolong_add(const Work* __restrict__
   const Work wk = work[blockIdx.x];
   const LInst& F = lf[wk.inst];
   const LInst& C = lc[wk.inst];
+  if (gated_off(C)) return;   // converged instance (Krylov iterations only)
   const int jf = wk.start + threadIdx.x;
   if (jf >= F.N) return;
   int fc[kMaxD];
@@ -945,6 +950,7 @@ __global__ void __launch_bounds__(kBlock) k_bb_solve(const int* __restrict__ ins
                                                      const TV* __restrict__ Lb, const TV* __restrict__ bvec,
                                                      TV* __restrict__ xvec) {
   const LInst& L = li[inst_list[blockIdx.x]];
+  if (gated_off(L)) return;   // converged instance (Krylov iterations only)
   const int T = L.n[0], m = L.N / T;
   const long long base = L.doff;
   __shared__ double ys[kBBMax * kBBMax];  // y then x (T * m <= 4096)
@@ -1169,6 +1175,7 @@ __global__ void __launch_bounds__(kDotLanes) k_dot(const Work* __restrict__ work
                                                    double* __restrict__ partial) {
   const Work wk = work[blockIdx.x];
   const LInst& L = li[wk.inst];
+  if (gated_off(L)) return;   // converged instance (Krylov iterations only)
   double v = 0;
 #pragma unroll
   for (int i = 0; i < kBlock / kDotLanes; ++i) {
@@ -1248,6 +1255,7 @@ __global__ void __launch_bounds__(kBlock) k_update_pq(const Work* __restrict__ w
                                                       double* __restrict__ partial) {
   const Work wk = work[blockIdx.x];
   const LInst& L = li[wk.inst];
+  if (gated_off(L)) return;   // converged instance (Krylov iterations only)
   const int j = wk.start + threadIdx.x;
   double v = 0;
   if (j < L.N) {
@@ -1278,6 +1286,7 @@ __global__ void __launch_bounds__(kBlock) k_update_xr(const Work* __restrict__ w
                                                       TV* __restrict__ r0, TV* __restrict__ d0) {
   const Work wk = work[blockIdx.x];
   const LInst& L = li[wk.inst];
+  if (gated_off(L)) return;   // converged instance (Krylov iterations only)
   const int j = wk.start + threadIdx.x;
   double v = 0;
   if (j < L.N) {
@@ -1682,6 +1691,7 @@ __global__ void __launch_bounds__(kBlock) k_bb_solve64(const int* __restrict__ i
                                                        const TV* __restrict__ bvec, TV* __restrict__ xvec) {
   constexpr int M = 64, CW = 16;
   const LInst& L = li[inst_list[blockIdx.x]];
+  if (gated_off(L)) return;   // converged instance (Krylov iterations only)
   const int T = L.n[0];
   const long long base = L.doff;
   __shared__ double ys[4096];
@@ -1815,6 +1825,7 @@ __global__ void __launch_bounds__(64) k_bb_solve16(const int* __restrict__ inst_
                                                    const TV* __restrict__ Lb, const TV* __restrict__ bvec,
                                                    TV* __restrict__ xvec) {
   const LInst& L = li[inst_list[blockIdx.x]];
+  if (gated_off(L)) return;   // converged instance (Krylov iterations only)
   const int T = L.n[0], m = L.N / T;
   const long long base = L.doff;
   __shared__ double ys[4096];           // y then x (T * m <= 4096, the coarsest-grid limit)
