@@ -2161,7 +2161,10 @@ __global__ void __launch_bounds__(kBlock) k_hash_fill(const Work* __restrict__ w
   const LInst& L = li[wk.inst];
   const int j = wk.start + threadIdx.x;
   if (j >= L.N) return;
-  unsigned h = (unsigned)(L.voff + j) * 2654435761u ^ (seed * 2246822519u + 0x9e3779b9u);
+  // hashed on the point's index within its instance, so that an instance's
+  // start vector (and its Chebyshev interval) does not depend on its place
+  // in the batch
+  unsigned h = (unsigned)j * 2654435761u ^ (seed * 2246822519u + 0x9e3779b9u);
   h ^= h >> 15; h *= 2246822519u; h ^= h >> 13; h *= 3266489917u; h ^= h >> 16;
   v[L.voff + j] = (TV)((double)(h & 0xffffff) / (double)0x800000 - 1.0);
 }

@@ -260,6 +260,22 @@ def test_adaptive_inner_tolerance():
         assert normal_relres(inst, a) <= 1e-6
 
 
+def test_batch_matches_single_solves():
+    # Instances of a ragged batch converge after different numbers of
+    # iterations; the Krylov kernels skip an instance once it has converged.
+    # Every instance's arithmetic is its own (per-instance reductions and
+    # scalars, no coupling between instances), so each batched answer equals
+    # the answer of the instance solved alone, bit for bit.
+    shapes = [(16, 24), (32, 16), (24, 48), (12, 12), (48, 32)]
+    insts = [as_dtype(W.reaction_diffusion_1d_ragged(i, s), "f32") for i, s in enumerate(shapes)]
+    _, zb, ib = gpu_solve(insts, "f32", out_f64=1)
+    assert len(set(ib["iters"].tolist())) > 1, ib["iters"]   # the instances do converge at different iterations
+    for k, inst in enumerate(insts):
+        _, z1, i1 = gpu_solve([inst], "f32", out_f64=1)
+        assert np.array_equal(z1[0], zb[k]), k
+        assert int(i1["iters"][0]) == int(ib["iters"][k])
+
+
 def test_time_operator_modes():
     # mpde_time_operator: every pass times positive and reports the
     # algorithmic bytes of its mode (K = 6 coefficient planes, FP32 vectors;
