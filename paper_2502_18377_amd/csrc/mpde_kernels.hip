@@ -1248,28 +1248,34 @@ __global__ void __launch_bounds__(kBlock) k_update_p(const Work* __restrict__ wo
 // rv = r - S z is the preconditioner's own final residual (the V-cycle's
 // smoother keeps it), so q = (r - rv) + beta q; partial p.q
 template <typename TV>
-__global__ void __launch_bounds__(kBlock) k_update_pq(const Work* __restrict__ work, const LInst* __restrict__ li,
-                                                      const double* __restrict__ beta, const TV* __restrict__ z,
-                                                      const TV* __restrict__ r, const TV* __restrict__ rv,
-                                                      TV* __restrict__ p, TV* __restrict__ q,
-                                                      double* __restrict__ partial) {
+// (one wavefront per work item, like k_dot: kBlock / 64 points per lane and
+// a cross-lane tree for the partial sum)
+__global__ void __launch_bounds__(kDotLanes) k_update_pq(const Work* __restrict__ work, const LInst* __restrict__ li,
+                                                         const double* __restrict__ beta, const TV* __restrict__ z,
+                                                         const TV* __restrict__ r, const TV* __restrict__ rv,
+                                                         TV* __restrict__ p, TV* __restrict__ q,
+                                                         double* __restrict__ partial) {
   const Work wk = work[blockIdx.x];
   const LInst& L = li[wk.inst];
   if (gated_off(L)) return;   // converged instance (Krylov iterations only)
-  const int j = wk.start + threadIdx.x;
+  const double bt = beta[wk.inst];
   double v = 0;
-  if (j < L.N) {
-    const long long g = L.voff + j;
-    const double bt = beta[wk.inst];
-    // (beta = 0 starts the recurrences: the old p and q are not read)
-    const double po = bt != 0.0 ? (double)p[g] : 0.0, qo = bt != 0.0 ? (double)q[g] : 0.0;
-    const TV pn = (TV)((double)z[g] + bt * po);
-    const TV qn = (TV)(((double)r[g] - (double)rv[g]) + bt * qo);
-    p[g] = pn;
-    q[g] = qn;
-    v = (double)pn * (double)qn;
+#pragma unroll
+  for (int i = 0; i < kBlock / kDotLanes; ++i) {
+    const int j = wk.start + threadIdx.x + kDotLanes * i;
+    if (j < L.N) {
+      const long long g = L.voff + j;
+      // (beta = 0 starts the recurrences: the old p and q are not read)
+      const double po = bt != 0.0 ? (double)p[g] : 0.0, qo = bt != 0.0 ? (double)q[g] : 0.0;
+      const TV pn = (TV)((double)z[g] + bt * po);
+      const TV qn = (TV)(((double)r[g] - (double)rv[g]) + bt * qo);
+      p[g] = pn;
+      q[g] = qn;
+      v = fma((double)pn, (double)qn, v);
+    }
   }
-  v = block_sum(v);
+#pragma unroll
+  for (int off = kDotLanes / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kDotLanes);
   if (threadIdx.x == 0) partial[blockIdx.x] = v;
 }
 
@@ -2010,7 +2016,7 @@ template <typename TV>
 void launch_update_pq(hipStream_t st, const Work* w, int nb, const LInst* li, const double* beta, const TV* z,
                       const TV* r, const TV* rv, TV* p, TV* q, double* partial) {
   if (nb <= 0) return;
-  hipLaunchKernelGGL((k_update_pq<TV>), GRID(nb), w, li, beta, z, r, rv, p, q, partial);
+  hipLaunchKernelGGL((k_update_pq<TV>), dim3((unsigned)nb), dim3(kDotLanes), 0, st, w, li, beta, z, r, rv, p, q, partial);
 }
 
 template <typename TV>
