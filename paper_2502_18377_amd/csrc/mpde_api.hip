@@ -733,6 +733,11 @@ struct Solver {
   TC* C(void* p) { return (TC*)p; }
 
   void finish(const Table& t, double* out) { launch_finish_sum(st, P->partial, t.d_bstart, P->B, out); }
+  // finish(t, out), then the PCG scalar update `op` from that sum (one launch)
+  void finish_scalars(const Table& t, double* out, int op, bool first) {
+    launch_finish_scalars(st, P->partial, t.d_bstart, P->B, out, op, first ? 1 : 0, P->itol2, P->rz, P->beta, P->alpha,
+                          P->r0n2, P->active, P->iters);
+  }
   // Descriptors to launch with: the gated copy inside the Krylov iterations.
   bool gate = false;
   const LInst* LD(const Level& L) const { return gate ? L.dg : L.d; }
@@ -935,28 +940,20 @@ struct Solver {
     if (L0.dense.nb() > 0) launch_fill<TV>(st, L0.dense.d, L0.dense.nb(), L0.d, V(L0.r), (TV)0);
     launch_update_pq<TV>(st, t.d, t.nb(), LD(L0), P->beta, V(P->zk), V(P->rk), V(L0.r), V(P->pk), V(P->qk),
                          P->partial);
-    finish(t, P->pq);
+    finish_scalars(t, P->pq, 1, false);   // alpha = rz / pq
   }
 
   // One PCG iteration (plain V-cycle preconditioner, no host interaction).
   void pcg_iter(bool first) {
-    const double* tol2 = P->itol2;
     Level& L0 = P->lv[0];
     const Table& t = L0.all;
-    const int B = P->B;
     vcycle(0, V(P->rk), V(P->zk), !first);   // after the first iteration update_xr wrote the start
     launch_dot<double, TV>(st, t.d, t.nb(), LD(L0), V(P->rk), V(P->zk), P->partial);
-    finish(t, P->rz_new);
-    launch_pcg_scalars(st, 0, B, first, tol2, P->rz_new, P->rz, P->beta, P->pq, P->alpha, P->rn2, P->r0n2,
-                       P->active, P->iters);
+    finish_scalars(t, P->rz_new, 0, first);
     update_pq();
-    launch_pcg_scalars(st, 1, B, 0, tol2, P->rz_new, P->rz, P->beta, P->pq, P->alpha, P->rn2, P->r0n2, P->active,
-                       P->iters);
     launch_update_xr<TV>(st, t.d, t.nb(), LD(L0), P->alpha, V(P->pk), V(P->qk), V(P->e), V(P->rk), P->partial,
                          V(L0.dinv), V(P->zk), V(L0.r), V(L0.dd));
-    finish(t, P->rn2);
-    launch_pcg_scalars(st, 2, B, 0, tol2, P->rz_new, P->rz, P->beta, P->pq, P->alpha, P->rn2, P->r0n2, P->active,
-                       P->iters);
+    finish_scalars(t, P->rn2, 2, false);
   }
 
   // Run `chunk` iterations through a captured graph (captured on first use
@@ -1037,7 +1034,8 @@ struct Solver {
       use_net = use_net_solve;
       vcycle(0, V(P->rk), V(P->zk), it > 0);   // after the first iteration update_xr wrote the start
       launch_dot<double, TV>(st, t.d, t.nb(), LD(L0), V(P->rk), V(P->zk), P->partial);
-      finish(t, P->rz_new);
+      if (flex) finish(t, P->rz_new);
+      else finish_scalars(t, P->rz_new, 0, it == 0);
       if (flex) {
         // Guard: a learned correction that is not a descent direction for
         // some active instance is replaced by the plain V-cycle.
@@ -1060,17 +1058,11 @@ struct Solver {
         launch_pcg_scalars(st, 3, B, it == 0, tol2, P->rz_new, P->rz, P->beta, P->rzp, P->alpha, P->rn2, P->r0n2,
                            P->active, P->iters);
         launch_copy_scale<TV, TV>(st, t.d, t.nb(), L0.d, V(P->zk), V(P->zp), nullptr, 0);
-      } else
-      launch_pcg_scalars(st, 0, B, it == 0, tol2, P->rz_new, P->rz, P->beta, P->pq, P->alpha, P->rn2, P->r0n2,
-                         P->active, P->iters);
+      }
       update_pq();
-      launch_pcg_scalars(st, 1, B, 0, tol2, P->rz_new, P->rz, P->beta, P->pq, P->alpha, P->rn2, P->r0n2, P->active,
-                         P->iters);
       launch_update_xr<TV>(st, t.d, t.nb(), LD(L0), P->alpha, V(P->pk), V(P->qk), V(P->e), V(P->rk), P->partial,
                          V(L0.dinv), V(P->zk), V(L0.r), V(L0.dd));
-      finish(t, P->rn2);
-      launch_pcg_scalars(st, 2, B, 0, tol2, P->rz_new, P->rz, P->beta, P->pq, P->alpha, P->rn2, P->r0n2, P->active,
-                         P->iters);
+      finish_scalars(t, P->rn2, 2, false);
       if (flex && use_net_solve && (it + 1) % 5 == 0) {
         // Stagnation guard: if the learned correction reduced the residual
         // more slowly than 0.8 per iteration over the last 5 iterations for

@@ -1230,6 +1230,34 @@ __global__ void k_pcg_scalars(int op, int B, int first, const double* __restrict
   }
 }
 
+// k_finish_sum into out (one of rz_new, pq, rn2), then the scalar update
+// of k_pcg_scalars op 0, 1 or 2 of the same instance from that sum, by the
+// thread that holds it (one launch instead of two).  The sum is handed to
+// the update as a value: out is not read back.
+__global__ void __launch_bounds__(kBlock) k_finish_scalars(const double* __restrict__ partial,
+                                                           const int* __restrict__ bstart, double* __restrict__ out,
+                                                           int op, int first, const double* __restrict__ tol2,
+                                                           double* __restrict__ rz, double* __restrict__ beta,
+                                                           double* __restrict__ alpha,
+                                                           const double* __restrict__ r0n2, int* __restrict__ active,
+                                                           int* __restrict__ iters) {
+  const int b = blockIdx.x;
+  double s = 0;
+  for (int i = bstart[b] + threadIdx.x; i < bstart[b + 1]; i += kBlock) s += partial[i];
+  s = block_sum(s);
+  if (threadIdx.x != 0) return;
+  out[b] = s;
+  if (op == 0) {   // s = r.z
+    beta[b] = (active[b] && !first && rz[b] != 0.0) ? s / rz[b] : 0.0;
+    rz[b] = s;
+  } else if (op == 1) {   // s = p.q
+    alpha[b] = (active[b] && s > 0.0 && isfinite(s)) ? rz[b] / s : 0.0;
+  } else if (active[b]) {   // s = ||r||^2
+    iters[b] += 1;
+    if (!(s > tol2[b] * r0n2[b])) active[b] = 0;   // converged or non-finite
+  }
+}
+
 // p = z + beta p
 template <typename TV>
 __global__ void __launch_bounds__(kBlock) k_update_p(const Work* __restrict__ work, const LInst* __restrict__ li,
@@ -1997,6 +2025,13 @@ void launch_dot(hipStream_t st, const Work* w, int nb, const LInst* li, const TV
 
 void launch_finish_sum(hipStream_t st, const double* partial, const int* bstart, int B, double* out) {
   hipLaunchKernelGGL(k_finish_sum, dim3(B), dim3(kBlock), 0, st, partial, bstart, B, out);
+}
+
+void launch_finish_scalars(hipStream_t st, const double* partial, const int* bstart, int B, double* out, int op,
+                           int first, const double* tol2, double* rz, double* beta, double* alpha,
+                           const double* r0n2, int* active, int* iters) {
+  hipLaunchKernelGGL(k_finish_scalars, dim3(B), dim3(kBlock), 0, st, partial, bstart, out, op, first, tol2, rz, beta,
+                     alpha, r0n2, active, iters);
 }
 
 void launch_pcg_scalars(hipStream_t st, int op, int B, int first, const double* tol2, double* rz_new, double* rz,

@@ -72,6 +72,12 @@ void launch_dense_apply(hipStream_t st, const Work* w, int nb, const LInst* li, 
 template <typename TA, typename TV>
 void launch_dot(hipStream_t st, const Work* w, int nb, const LInst* li, const TV* a, const TV* b, double* partial);
 void launch_finish_sum(hipStream_t st, const double* partial, const int* bstart, int B, double* out);
+// Per-instance sum of the block partials into out, then the pcg_scalars
+// update op (0: beta and rz from r.z, 1: alpha from p.q, 2: convergence
+// test of ||r||^2) from that sum, in one launch.
+void launch_finish_scalars(hipStream_t st, const double* partial, const int* bstart, int B, double* out, int op,
+                           int first, const double* tol2, double* rz, double* beta, double* alpha,
+                           const double* r0n2, int* active, int* iters);
 // (tol2: per-instance squared relative tolerance of the inner solve, device)
 void launch_pcg_scalars(hipStream_t st, int op, int B, int first, const double* tol2, double* rz_new, double* rz,
                         double* beta, double* pq, double* alpha, double* rn2, double* r0n2, int* active,
