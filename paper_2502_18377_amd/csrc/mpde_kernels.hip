@@ -1312,31 +1312,36 @@ __global__ void __launch_bounds__(kDotLanes) k_update_pq(const Work* __restrict_
 // (as k_cheb_init with b = the new r), on instances for which the level is
 // smoothed: z0 = 0, r0 = r, d0 = D^-1 r / theta.
 template <typename TV>
-__global__ void __launch_bounds__(kBlock) k_update_xr(const Work* __restrict__ work, const LInst* __restrict__ li,
-                                                      const double* __restrict__ alpha, const TV* __restrict__ p,
-                                                      const TV* __restrict__ q, TV* __restrict__ x,
-                                                      TV* __restrict__ r, double* __restrict__ partial,
-                                                      const TV* __restrict__ dinv, TV* __restrict__ z0,
-                                                      TV* __restrict__ r0, TV* __restrict__ d0) {
+__global__ void __launch_bounds__(kDotLanes) k_update_xr(const Work* __restrict__ work, const LInst* __restrict__ li,
+                                                         const double* __restrict__ alpha, const TV* __restrict__ p,
+                                                         const TV* __restrict__ q, TV* __restrict__ x,
+                                                         TV* __restrict__ r, double* __restrict__ partial,
+                                                         const TV* __restrict__ dinv, TV* __restrict__ z0,
+                                                         TV* __restrict__ r0, TV* __restrict__ d0) {
   const Work wk = work[blockIdx.x];
   const LInst& L = li[wk.inst];
   if (gated_off(L)) return;   // converged instance (Krylov iterations only)
-  const int j = wk.start + threadIdx.x;
+  const double al = alpha[wk.inst];
+  const bool start = z0 && !L.coarsest;
   double v = 0;
-  if (j < L.N) {
-    const long long g = L.voff + j;
-    const double al = alpha[wk.inst];
-    x[g] = (TV)((double)x[g] + al * (double)p[g]);
-    const TV rr = (TV)((double)r[g] - al * (double)q[g]);
-    r[g] = rr;
-    v = (double)rr * (double)rr;
-    if (z0 && !L.coarsest) {
-      z0[g] = (TV)0;
-      r0[g] = rr;
-      d0[g] = (TV)((double)dinv[g] * (double)rr / L.cheb_theta);
+#pragma unroll
+  for (int i = 0; i < kBlock / kDotLanes; ++i) {
+    const int j = wk.start + threadIdx.x + kDotLanes * i;
+    if (j < L.N) {
+      const long long g = L.voff + j;
+      x[g] = (TV)((double)x[g] + al * (double)p[g]);
+      const TV rr = (TV)((double)r[g] - al * (double)q[g]);
+      r[g] = rr;
+      v = fma((double)rr, (double)rr, v);
+      if (start) {
+        z0[g] = (TV)0;
+        r0[g] = rr;
+        d0[g] = (TV)((double)dinv[g] * (double)rr / L.cheb_theta);
+      }
     }
   }
-  v = block_sum(v);
+#pragma unroll
+  for (int off = kDotLanes / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kDotLanes);
   if (threadIdx.x == 0) partial[blockIdx.x] = v;
 }
 
@@ -2058,7 +2063,8 @@ template <typename TV>
 void launch_update_xr(hipStream_t st, const Work* w, int nb, const LInst* li, const double* alpha, const TV* p,
                       const TV* q, TV* x, TV* r, double* partial, const TV* dinv, TV* z0, TV* r0, TV* d0) {
   if (nb <= 0) return;
-  hipLaunchKernelGGL((k_update_xr<TV>), GRID(nb), w, li, alpha, p, q, x, r, partial, dinv, z0, r0, d0);
+  hipLaunchKernelGGL((k_update_xr<TV>), dim3((unsigned)nb), dim3(kDotLanes), 0, st, w, li, alpha, p, q, x, r, partial,
+                     dinv, z0, r0, d0);
 }
 
 template <typename TS, typename TD>
